@@ -1,0 +1,166 @@
+"""CPU oracle for the ImprovedGS+ densification hot path (arXiv 2603.08661).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
+CPU-baseline leg of ``bench.py``; never by the product path. It shares no
+code with the GPU library. The arithmetic lives in ``igsp_oracle.c`` (plain
+C, int64-exact through the gradient and orientation bins, FP64 after);
+this module only marshals numpy arrays.
+
+Edge map: Sec. 2.1 (grayscale, 5x5 Gaussian blur, Sobel magnitude and
+orientation, non-maximum suppression, median normalisation).
+Long-Axis-Split: Sec. 2.2, Algorithms 1 and 2, constants alpha = 0.5,
+gamma = 0.85, beta = 0.6.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# The split constants printed in Sec. 2.2 (paragraph after Algorithm 1).
+ALPHA, GAMMA, BETA = 0.5, 0.85, 0.6
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (-O2, OpenMP across views)."""
+    if force or not os.path.exists(_LIB_PATH):
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+             os.path.join(_HERE, "igsp_oracle.c"), "-o", _LIB_PATH + ".tmp", "-lm"])
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.orc_blur_taps.argtypes = [vp]
+        L.orc_blur_taps.restype = None
+        L.orc_bin.argtypes = [i64, i64]
+        L.orc_bin.restype = i32
+        L.orc_edge_view.argtypes = [vp, i32, i32] + [vp] * 12
+        L.orc_edge_view.restype = i64
+        L.orc_edge_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32]
+        L.orc_edge_batch.restype = None
+        L.orc_quat_to_R.argtypes = [vp, vp]
+        L.orc_quat_to_R.restype = None
+        L.orc_opacity.argtypes = [dbl, dbl]
+        L.orc_opacity.restype = dbl
+        L.orc_las.argtypes = [i64, i64, vp, vp, vp, vp, vp, i32, vp, dbl, dbl, dbl,
+                              vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_las.restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def blur_taps() -> np.ndarray:
+    out = np.zeros(5, np.int64)
+    lib().orc_blur_taps(_p(out))
+    return out
+
+
+def bin_of(gx: int, gy: int) -> int:
+    """Orientation bin: 0 horizontal, 1 vertical, 2 diagonal gx*gy>0, 3 otherwise."""
+    return int(lib().orc_bin(int(gx), int(gy)))
+
+
+def edge_view(rgb: np.ndarray) -> dict:
+    """Every stage of the edge pipeline for one (H, W, 3) uint8 view."""
+    rgb = np.ascontiguousarray(rgb, np.uint8)
+    H, W = rgb.shape[:2]
+    o = {k: np.zeros((H, W), np.int64) for k in ("gray", "b", "gx", "gy", "M")}
+    o["bin"] = np.zeros((H, W), np.uint8)
+    o["keep"] = np.zeros((H, W), np.uint8)
+    for k in ("m", "E", "margin"):
+        o[k] = np.zeros((H, W), np.float64)
+    med = np.zeros(1, np.float64)
+    Mmed = np.zeros(1, np.int64)
+    n = lib().orc_edge_view(_p(rgb), W, H, _p(o["gray"]), _p(o["b"]), _p(o["gx"]), _p(o["gy"]),
+                            _p(o["M"]), _p(o["bin"]), _p(o["keep"]), _p(o["m"]), _p(o["E"]),
+                            _p(o["margin"]), _p(med), _p(Mmed))
+    if n < 0:
+        raise ValueError("views must be at least 3x3")
+    o["n"], o["med"], o["Mmed"] = int(n), float(med[0]), int(Mmed[0])
+    return o
+
+
+def edge_batch(rgb: np.ndarray, widths, heights, in_offset, out_offset, out_floats: int,
+               threads: int = 0, want_keep: bool = False) -> dict:
+    """Normalised maps (FP64) for packed views; layout as in the GPU call."""
+    W = np.ascontiguousarray(widths, np.int32)
+    H = np.ascontiguousarray(heights, np.int32)
+    if (W < 3).any() or (H < 3).any():
+        raise ValueError("views must be at least 3x3")
+    io = np.ascontiguousarray(in_offset, np.int64)
+    oo = np.ascontiguousarray(out_offset, np.int64)
+    n = W.shape[0]
+    E = np.zeros(out_floats, np.float64)
+    keep = np.zeros(out_floats, np.uint8) if want_keep else None
+    med = np.zeros(n, np.float64)
+    ns = np.zeros(n, np.int64)
+    lib().orc_edge_batch(_p(np.ascontiguousarray(rgb, np.uint8)), n, _p(W), _p(H), _p(io), _p(oo),
+                         _p(E), _p(keep), _p(med), _p(ns), int(threads))
+    out = {"E": E, "med": med, "n": ns}
+    if want_keep:
+        out["keep"] = keep
+    return out
+
+
+def quat_to_R(q) -> np.ndarray:
+    q = np.ascontiguousarray(q, np.float64)
+    R = np.zeros(9, np.float64)
+    lib().orc_quat_to_R(_p(q), _p(R))
+    return R.reshape(3, 3)
+
+
+def opacity_update(o: float, beta: float = BETA) -> float:
+    return float(lib().orc_opacity(float(o), float(beta)))
+
+
+def las(N: int, means, log_scales, quats, opacity_logits, mask, feats=None,
+        alpha: float = ALPHA, gamma: float = GAMMA, beta: float = BETA) -> dict:
+    """Long-Axis-Split in place over arrays of `capacity` rows (FP64 results).
+
+    means (cap,3), log_scales (cap,3), quats (cap,4), opacity_logits (cap,),
+    feats (cap,F) or None, all float32; mask (>= N,) uint8.
+    """
+    means = np.ascontiguousarray(means, np.float32)
+    ls = np.ascontiguousarray(log_scales, np.float32)
+    q = np.ascontiguousarray(quats, np.float32)
+    op = np.ascontiguousarray(opacity_logits, np.float32)
+    cap = means.shape[0]
+    F = 0 if feats is None else int(feats.shape[1])
+    f = np.zeros((cap, max(F, 1)), np.float32) if feats is None else np.ascontiguousarray(feats, np.float32)
+    mk = np.zeros(cap, np.uint8)
+    mk[:min(cap, mask.shape[0])] = np.asarray(mask, np.uint8)[:cap]
+    out = {
+        "means": np.zeros((cap, 3)), "log_scales": np.zeros((cap, 3)), "quats": np.zeros((cap, 4)),
+        "opacity_logits": np.zeros(cap), "feats": np.zeros((cap, max(F, 1))),
+        "split_idx": np.zeros(cap, np.int32), "axis": np.zeros(cap, np.int32),
+    }
+    K = np.zeros(1, np.int64)
+    cnt = np.zeros(1, np.int64)
+    st = lib().orc_las(int(N), cap, _p(means), _p(ls), _p(q), _p(op), _p(f), F, _p(mk),
+                       alpha, gamma, beta, _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]),
+                       _p(out["opacity_logits"]), _p(out["feats"]), _p(out["split_idx"]),
+                       _p(out["axis"]), _p(K), _p(cnt))
+    out["status"], out["K"], out["count"] = int(st), int(K[0]), int(cnt[0])
+    out["split_idx"] = out["split_idx"][:out["K"]] if st == 0 else out["split_idx"][:0]
+    out["axis"] = out["axis"][:out["K"]] if st == 0 else out["axis"][:0]
+    if F == 0:
+        out["feats"] = out["feats"][:, :0]
+    return out
