@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Throughput of the densification hot path on one MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+edge-score maps of every view (grayscale, blur, Sobel, suppression, median
+normalisation) followed by Long-Axis-Split of the selected Gaussians. The
+default workload is the full densification step: 300 views of widths
+1000-2473 (BF16 intermediate storage, every view in one launch per stage)
+and LAS on 3M Gaussians with 20% selected, recorded once as a HIP graph and
+replayed per step. The plain per-view FP32 form of the same step is timed
+beside it, the dominant kernel is timed live with HIP events on its own
+stream for the roofline, and the CPU oracle is timed on a bounded sample.
+
+Prints one JSON line. Inputs are resident in HBM before timing starts; the
+Gaussian count grows on the device from step to step (each step splits the
+same selected rows again, so every step does the same split work).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edge-map megapixels/s + Gaussians split/s, batched-FP16 vs plain-FP32, % HBM peak"
+HBM_PEAK_GBS = 8000.0
+STORE_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def percentile_ms(events_pairs):
+    return float(np.mean([a.elapsed_time(b) for a, b in events_pairs]))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=5, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--precision", default=None, help="override the workload's intermediate storage")
+    ap.add_argument("--seg-rows", type=int, default=0)
+    ap.add_argument("--wg-waves", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-view FP32 comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--stage-reps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
+                                   "(views would shard with no exchange, see the design notes)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2603_08661_amd as igsp
+    import synth
+
+    dev = torch.device("cuda:0")
+    w = synth.workload(args.workload)
+    prec = args.precision or w.precision
+    t0 = time.time()
+    vb = w.render()
+    log(f"workload {w.index}: {vb.n} views, {vb.pixels / 1e6:.1f} MPx rendered in {time.time() - t0:.1f}s")
+    img = torch.from_numpy(np.concatenate([vb.rgb, np.zeros(16, np.uint8)])).to(dev)
+    out = torch.zeros(vb.out_floats, dtype=torch.float32, device=dev)
+    views = (vb.widths, vb.heights, vb.in_offset, vb.out_offset)
+    mpx = vb.pixels / 1e6
+
+    has_las = w.n_gauss > 0
+    steps_total = 2 * (args.warmup + args.steps) + args.stage_reps + 4
+    if has_las:
+        g = w.gaussian_set()
+        mk = w.split_mask()
+        N0, K = w.n_gauss, w.n_split
+        cap = N0 + K * steps_total
+        G = {}
+        for k in ("means", "log_scales", "quats", "opacity_logits"):
+            a = getattr(g, k)
+            G[k] = torch.zeros((cap,) + a.shape[1:], dtype=torch.float32, device=dev)
+            G[k][:N0] = torch.from_numpy(a).to(dev)
+        G["count"] = torch.tensor([N0], dtype=torch.int64, device=dev)
+        mask = torch.zeros(cap, dtype=torch.uint8, device=dev)
+        mask[:N0] = torch.from_numpy(mk).to(dev)
+        sidx = torch.zeros(cap, dtype=torch.int32, device=dev)
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+        log(f"LAS: N={N0} K={K} capacity={cap}")
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.Stream()
+    batched = w.batched or args.workload == 5
+
+    def edge(p, b, ev=None):
+        igsp.edge_importance(img, views, out, precision=p, batched=b, seg_rows=args.seg_rows,
+                             wg_waves=args.wg_waves, stage_events=ev, stream=stream)
+
+    def las():
+        igsp.long_axis_split(G["means"], G["log_scales"], G["quats"], G["opacity_logits"], G["count"], mask,
+                             sidx, status, stream=stream)
+
+    def timed(fn, warm, reps):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - w0) * 1e3 / reps
+        return e0.elapsed_time(e1) / reps, wall
+
+    # ---- primary form: batched, reduced-precision storage, graph-captured step
+    if w.graph:
+        with torch.cuda.stream(stream):
+            step = igsp.Step(img, views, out, G, mask, sidx, status, precision=prec, batched=True,
+                             seg_rows=args.seg_rows, wg_waves=args.wg_waves, stream=stream)
+        run_primary = lambda: step.launch(stream)  # noqa: E731
+        form = f"batched {prec} + LAS, one HIP graph per step"
+    else:
+        def run_primary():
+            edge(prec, batched)
+            if has_las:
+                las()
+        form = f"{'batched' if batched else 'plain per-view'} {prec}" + (" + LAS" if has_las else "")
+    ms, wall = timed(run_primary, args.warmup, args.steps)
+    log(f"primary ({form}): {ms:.3f} ms/step (wall {wall:.3f})")
+    if has_las:
+        assert int(status.item()) == 0, "split reported a capacity error"
+
+    # ---- live stage timing of the dominant kernel (same configuration, eager)
+    pairs = {k: [] for k in ("fused", "select", "normalise", "edge")}
+    for _ in range(args.stage_reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        edge(prec, True, ev)
+        torch.cuda.synchronize()
+        pairs["fused"].append((ev[0], ev[1]))
+        pairs["select"].append((ev[1], ev[2]))
+        pairs["normalise"].append((ev[2], ev[3]))
+        pairs["edge"].append((ev[0], ev[3]))
+    stage_ms = {k: percentile_ms(v) for k, v in pairs.items()}
+    las_ms = None
+    if has_las:
+        las_ms, _ = timed(las, 1, args.stage_reps)
+    sb = STORE_BYTES[prec]
+    fused_bytes = vb.pixels * (3 + sb)
+    achieved = fused_bytes / (stage_ms["fused"] * 1e-3) / 1e9
+    log(f"stages: {stage_ms}, las {las_ms}")
+
+    # ---- plain per-view FP32 form of the same step
+    plain = None
+    if not args.no_plain:
+        def run_plain():
+            edge("fp32", False)
+            if has_las:
+                las()
+        pms, pwall = timed(run_plain, 1, max(1, min(args.steps, 5)))
+        plain = {"form": "plain per-view fp32" + (" + LAS" if has_las else ""), "ms_per_step": round(pms, 4),
+                 "mpx_per_s": round(mpx / (pms * 1e-3), 1)}
+        if has_las:
+            plain["gaussians_split_per_s"] = round(K / (pms * 1e-3), 1)
+        log(f"plain fp32: {pms:.3f} ms/step")
+
+    # ---- CPU oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        v0 = vb.view(0)
+        t1 = time.perf_counter()
+        oracle.edge_view(v0)
+        tv = time.perf_counter() - t1
+        per_thread = max(1, int(round(args.cpu_seconds / max(tv, 1e-3) / 2)))
+        nsamp = min(vb.n, threads * per_thread)
+        sel = np.arange(nsamp)
+        sub = synth.pack_views([vb.view(int(v)) for v in sel])
+        t1 = time.perf_counter()
+        oracle.edge_batch(sub.rgb, sub.widths, sub.heights, sub.in_offset, sub.out_offset, sub.out_floats,
+                          threads=threads)
+        te = time.perf_counter() - t1
+        cpu = {"value": round(sub.pixels / 1e6 / te, 3), "unit": "MPx/s", "cores": threads, "kind": "oracle",
+               "sample": f"edge maps of the first {nsamp} views ({sub.pixels / 1e6:.1f} MPx) of the same "
+                         f"workload, views spread over {threads} threads, {te:.1f}s"}
+        if has_las:
+            h = {k: G[k][:N0].cpu().numpy() for k in ("means", "log_scales", "quats", "opacity_logits")}
+            n_l = min(N0, 1_000_000)
+            t1 = time.perf_counter()
+            r = oracle.las(n_l, h["means"][:n_l], h["log_scales"][:n_l], h["quats"][:n_l],
+                           h["opacity_logits"][:n_l], mk[:n_l])
+            tl = time.perf_counter() - t1
+            cpu["gaussians_split_per_s"] = round(r["K"] / tl, 1) if r["status"] == 0 else None
+            cpu["sample"] += f"; split of the first {n_l} Gaussians ({r['K']} selected would need {n_l + r['K']} " \
+                             f"rows) on 1 thread, {tl:.2f}s"
+        log(f"cpu baseline: {cpu}")
+
+    res = {
+        "metric": METRIC,
+        "value": round(mpx / (ms * 1e-3), 1),
+        "unit": "MPx/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "views": vb.n, "megapixels": round(mpx, 2),
+                   "intermediate": prec, "form": form, "gaussians": w.n_gauss, "split": w.n_split,
+                   "arithmetic": "int32 exact through Sobel, fp32 magnitude/suppression/median/LAS"},
+        "wall_ms_per_step": round(wall, 4),
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "roofline": {"bound": "hbm", "kernel": "edge_fused", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes_per_px": 3 + sb,
+                     "bytes_per_launch": int(fused_bytes)},
+        "edge_pipeline": {"ms": round(stage_ms["edge"], 4),
+                          "mpx_per_s": round(mpx / (stage_ms["edge"] * 1e-3), 1),
+                          "algorithmic_GBps": round(vb.pixels * 7 / (stage_ms["edge"] * 1e-3) / 1e9, 1),
+                          "frac_of_hbm_peak": round(vb.pixels * 7 / (stage_ms["edge"] * 1e-3) / 1e9
+                                                    / HBM_PEAK_GBS, 4)},
+    }
+    if has_las:
+        res["gaussians_split_per_s"] = round(K / (ms * 1e-3), 1)
+        las_bytes = N0 + 120 * K
+        res["las"] = {"ms": round(las_ms, 4), "gaussians_split_per_s": round(K / (las_ms * 1e-3), 1),
+                      "algorithmic_GBps": round(las_bytes / (las_ms * 1e-3) / 1e9, 1)}
+    if plain:
+        res["plain_fp32"] = plain
+        res["speedup_vs_plain_fp32"] = round(plain["ms_per_step"] / ms, 3)
+    if cpu:
+        res["cpu_baseline"] = cpu
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

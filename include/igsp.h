@@ -1,0 +1,216 @@
+/*
+ * igsp.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of the ImprovedGS+ densification strategy (arXiv 2603.08661):
+ *
+ *   edge_importance  -- per-view edge-score importance maps (Sec. 2.1):
+ *                       grayscale, 5x5 Gaussian blur, Sobel magnitude and
+ *                       orientation, non-maximum suppression along the
+ *                       gradient, median normalisation;
+ *   long_axis_split  -- Long-Axis-Split of selected Gaussians (Sec. 2.2,
+ *                       Algorithm 1 with the column-extraction transform of
+ *                       Algorithm 2).
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked (device) are HIP device memory on the current device;
+ *     pointers marked (host) are host memory read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; calls return without waiting for the GPU.
+ *   - The caller owns every buffer passed in. The library owns only its
+ *     plans (device view tables, work lists, histograms, intermediate maps,
+ *     split workspaces), created on the first call with a given geometry and
+ *     reused afterwards; igsp_release_plans() frees them.
+ *   - A call that creates a plan may allocate device memory and is therefore
+ *     not capturable into a HIP graph; repeated calls with the same geometry
+ *     allocate nothing, never read device memory back to the host, and can be
+ *     captured (see igsp_step_*).
+ *   - Errors detectable on the host return a negative status and enqueue
+ *     nothing. No C++ exception crosses this boundary.
+ *   - Calls on one device that share a plan must be ordered (one stream, or
+ *     synchronised): the plan's intermediate buffers are reused.
+ */
+#ifndef IGSP_H
+#define IGSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IGSP_OK = 0,
+  IGSP_ERR_NULL = -1,        /* a required pointer is NULL                       */
+  IGSP_ERR_DIMS = -2,        /* a view below 3x3, W*H >= 2^31, n_views < 0,
+                                negative offsets or counts                       */
+  IGSP_ERR_ALIGN = -3,       /* `images` not 16-byte aligned                     */
+  IGSP_ERR_OVERLAP = -4,     /* input and output byte ranges overlap             */
+  IGSP_ERR_PARAM = -5,       /* unknown precision, bad tile option, feat_dim < 0,
+                                alpha/gamma/beta outside (0, 1]                  */
+  IGSP_ERR_CAPACITY = -6,    /* (device status) N + K > capacity: nothing split  */
+  IGSP_ERR_HIP = -7,         /* a HIP runtime call failed (no device, OOM, ...)  */
+  IGSP_ERR_UNSUPPORTED = -8  /* the current device is not gfx950                 */
+} igsp_status;
+
+/* ------------------------------------------------------------------------ */
+/* Edge-score importance maps (Sec. 2.1)                                     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * One view. Its pixels are packed 8-bit R,G,B bytes, row-major, row pitch
+ * 3*width bytes, starting `in_offset` bytes after `images` (any byte
+ * offset). Its map is width*height float32 values, row-major, row pitch
+ * `width`, starting `out_offset` floats after `out_maps`.
+ * Requires width >= 3, height >= 3, width*height < 2^31.
+ */
+typedef struct {
+  int32_t width;
+  int32_t height;
+  int64_t in_offset;
+  int64_t out_offset;
+} igsp_view;
+
+/* Storage type of the one intermediate that reaches HBM: the thinned
+   (suppressed) gradient magnitude kept between the stencil pass and the
+   normalisation. Arithmetic is integer-exact through the gradient and FP32
+   after it in every mode; maps are float32 in every mode. */
+typedef enum { IGSP_FP32 = 0, IGSP_FP16 = 1, IGSP_BF16 = 2 } igsp_precision;
+
+typedef struct {
+  int32_t precision;     /* igsp_precision                                    */
+  int32_t batched;       /* 1: every view in one launch per stage (default);
+                            0: the plain form, each view processed by its own
+                            sequence of launches                              */
+  int32_t seg_rows;      /* output rows per wavefront segment; 0 = tuned      */
+  int32_t wg_waves;      /* wavefronts per work-group (1, 2, 4, 8); 0 = tuned */
+  float* medians;        /* (device, optional) [n_views]: the median surviving
+                            magnitude of each view, in DN per pixel of an
+                            unnormalised Sobel, as stored (0 if none survive) */
+  int32_t* survivors;    /* (device, optional) [n_views]: surviving pixels    */
+  void** stage_events;   /* (host, optional) 4 hipEvent_t recorded on `stream`
+                            before the stencil pass, after it, after the median
+                            selection and after the normalisation (batched
+                            form; the plain form records the last three after
+                            its final view). Profiling only: no work changes.
+                            Ignored by igsp_step_create.                       */
+} igsp_edge_opts;
+
+/*
+ * Edge-score importance map of every view (Sec. 2.1). For each view:
+ *   gray  = 299 R + 587 G + 114 B (BT.601 luma x 1000, exact);
+ *   blur  = binomial 5x5 Gaussian, taps (1,4,6,4,1)/16 per axis;
+ *   gx,gy = unnormalised Sobel; M = gx^2 + gy^2;
+ *   orientation quantised to the nearest of 0/45/90/135 degrees;
+ *   a pixel survives iff M(p) > M(p-d) and M(p) >= M(p+d) and M(p) > 0, d the
+ *   unit step along its gradient (ties: strict toward -d);
+ *   map = sqrt(M) / (lower median of sqrt(M) over the view's survivors) at
+ *   survivors, 0 elsewhere (0 everywhere if none survive).
+ * Borders mirror without repeating the edge pixel (reflect-101).
+ *
+ * images   (device) the packed views; must be 16-byte aligned.
+ * views    (host)   [n_views] geometry, see igsp_view.
+ * n_views  number of views; 0 is a no-op returning IGSP_OK.
+ * out_maps (device) float32 output, see igsp_view. May not overlap images.
+ * opts     (host, optional) NULL = batched, FP32, tuned tiles.
+ * stream   hipStream_t or NULL.
+ */
+igsp_status edge_importance(const uint8_t* images, const igsp_view* views, int32_t n_views,
+                            float* out_maps, const igsp_edge_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Long-Axis-Split (Sec. 2.2, Algorithms 1 and 2)                            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Gaussian parameters as structure-of-arrays, float32, `capacity` rows each
+ * (device). Rows [0, N) are live, N = *count. Scales are stored as logs,
+ * opacity as a logit, rotation as a quaternion (w, x, y, z), not necessarily
+ * normalised (a zero quaternion is read as the identity).
+ */
+typedef struct {
+  float* means;            /* (device) [capacity][3]                          */
+  float* log_scales;       /* (device) [capacity][3]                          */
+  float* quats;            /* (device) [capacity][4]                          */
+  float* opacity_logits;   /* (device) [capacity]                             */
+  float* features;         /* (device) [capacity][feat_dim], NULL if 0        */
+  int32_t feat_dim;        /* >= 0                                            */
+  int64_t* count;          /* (device) scalar N; becomes N + K on success     */
+  int64_t capacity;        /* rows allocated, >= 0                            */
+} igsp_gaussians;
+
+/* Shrink factor of the longest axis (also scales the child offset), shrink
+   factor of the other axes, opacity factor; NULL = 0.5, 0.85, 0.6, the
+   values the paper uses (Sec. 2.2). Each must lie in (0, 1]. */
+typedef struct {
+  float alpha;
+  float gamma;
+  float beta;
+} igsp_las_params;
+
+typedef struct {
+  int32_t* split_idx;      /* (device) [capacity]: the first K entries become
+                              the split rows in ascending order               */
+  int32_t* status;         /* (device) scalar: IGSP_OK or IGSP_ERR_CAPACITY   */
+  int64_t* n_split;        /* (device, optional) scalar K                     */
+} igsp_las_out;
+
+/*
+ * Split every live row i with mask[i] != 0, in place (Sec. 2.2, Alg. 1):
+ * l = index of the largest log-scale (lowest index on ties);
+ * log-scales: s_l += log(alpha), the others += log(gamma);
+ * opacity: o = logit(beta * sigmoid(o));
+ * d = alpha * exp(s_l) * (column l of R(q)), read as the three entries
+ * R[l], R[l+3], R[l+6] of the flat row-major matrix (Alg. 2);
+ * row i becomes the first child (mean + d), row N + r the second child
+ * (mean - d, same scales, opacity, quaternion and features), r = rank of i
+ * among the selected rows.
+ * All or nothing: if N + K > capacity, nothing is written except
+ * *status = IGSP_ERR_CAPACITY (and *n_split = K); *count stays N.
+ * mask (device) uint8 [capacity], entries [0, N) read.
+ * Calling twice splits twice (the operation is not idempotent).
+ */
+igsp_status long_axis_split(const igsp_gaussians* g, const uint8_t* mask, const igsp_las_out* out,
+                            const igsp_las_params* params, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* One densification step as a HIP graph                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct igsp_step igsp_step;
+
+/*
+ * Record one densification step -- edge_importance over the given views
+ * followed by long_axis_split -- into a HIP graph and instantiate it. The
+ * plans are created first (outside the capture), so the graph holds only
+ * kernel launches. Arguments as for the two calls; every pointer is baked
+ * into the graph, so the buffers must outlive it. The live count stays on
+ * the device: the graph remains valid as N grows.
+ * step (host, out) receives the handle.
+ */
+igsp_status igsp_step_create(const uint8_t* images, const igsp_view* views, int32_t n_views,
+                             float* out_maps, const igsp_edge_opts* opts, const igsp_gaussians* g,
+                             const uint8_t* mask, const igsp_las_out* out, const igsp_las_params* params,
+                             void* stream, igsp_step** step);
+/* Launch the recorded step on `stream`. */
+igsp_status igsp_step_launch(igsp_step* step, void* stream);
+/* Destroy the graph (after the launches that use it have finished). */
+void igsp_step_destroy(igsp_step* step);
+
+/* ------------------------------------------------------------------------ */
+/* Utilities                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Static English text for a status code. */
+const char* igsp_status_string(int32_t status);
+
+/* Free every plan and workspace on every device (the caller must ensure no
+   enqueued work still uses them). */
+void igsp_release_plans(void);
+
+/* Library version, for the binding's load check. */
+int32_t igsp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IGSP_H */

@@ -1,0 +1,374 @@
+// Host layer of libigsp: the C ABI entry points, the plan cache (device view
+// tables, work lists, median workspaces, intermediate maps), the launch
+// sequence of each form, and the graph-captured densification step.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "igsp_internal.h"
+#include "validate.h"
+
+namespace igsp {
+namespace {
+
+constexpr int kFlatChunk = 16384;  // pixels per work-group of the element-wise passes
+constexpr int kMaxPlans = 8;
+
+std::mutex g_mu;
+
+struct DeviceInfo {
+  bool checked = false;
+  bool ok = false;
+};
+std::map<int, DeviceInfo> g_dev;
+
+igsp_status check_device(int* dev_out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return IGSP_ERR_HIP;
+  DeviceInfo& d = g_dev[dev];
+  if (!d.checked) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return IGSP_ERR_HIP;
+    d.ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    d.checked = true;
+  }
+  *dev_out = dev;
+  return d.ok ? IGSP_OK : IGSP_ERR_UNSUPPORTED;
+}
+
+template <class T>
+hipError_t upload(T** dptr, const std::vector<T>& v) {
+  *dptr = nullptr;
+  if (v.empty()) return hipSuccess;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dptr), v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// ------------------------------------------------------------------ edge
+
+struct EdgeKey {
+  int device;
+  int precision, seg_rows, wg_waves;
+  std::vector<igsp_view> views;
+  bool operator==(const EdgeKey& o) const {
+    if (device != o.device || precision != o.precision || seg_rows != o.seg_rows || wg_waves != o.wg_waves ||
+        views.size() != o.views.size())
+      return false;
+    return std::memcmp(views.data(), o.views.data(), views.size() * sizeof(igsp_view)) == 0;
+  }
+};
+
+struct EdgePlan {
+  EdgeKey key;
+  int n_views = 0;
+  ViewDesc* d_views = nullptr;
+  EdgeItem* d_items = nullptr;
+  FlatItem* d_flat = nullptr;
+  std::vector<int> item_begin, flat_begin;  // per view, size n_views + 1
+  void* d_map = nullptr;
+  uint32_t* d_hist = nullptr;
+  uint32_t* d_rhist = nullptr;
+  MedState* d_state = nullptr;
+  ~EdgePlan() {
+    (void)hipFree(d_views); (void)hipFree(d_items); (void)hipFree(d_flat); (void)hipFree(d_map);
+    (void)hipFree(d_hist); (void)hipFree(d_rhist); (void)hipFree(d_state);
+  }
+};
+
+std::list<std::shared_ptr<EdgePlan>> g_edge_plans;  // most recently used first
+
+int default_seg_rows() { return 64; }
+int default_wg_waves() { return 4; }
+
+igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) {
+  auto plan = std::make_shared<EdgePlan>();
+  plan->key = key;
+  const int n = (int)key.views.size();
+  plan->n_views = n;
+  const int band = key.seg_rows * key.wg_waves;
+  const int esz = key.precision == IGSP_FP32 ? 4 : 2;
+  std::vector<ViewDesc> vd(n);
+  std::vector<EdgeItem> items;
+  std::vector<FlatItem> flat;
+  plan->item_begin.resize(n + 1);
+  plan->flat_begin.resize(n + 1);
+  int64_t map_elems = 0;
+  for (int v = 0; v < n; ++v) {
+    const igsp_view& d = key.views[v];
+    vd[v] = ViewDesc{d.width, d.height, d.in_offset, d.out_offset, map_elems};
+    const int64_t npx = (int64_t)d.width * d.height;
+    map_elems += (npx + 63) / 64 * 64;
+    plan->item_begin[v] = (int)items.size();
+    for (int x0 = 0; x0 < d.width; x0 += kStripCols)
+      for (int y0 = 0; y0 < d.height; y0 += band)
+        items.push_back(EdgeItem{v, x0, y0, std::min(band, d.height - y0)});
+    plan->flat_begin[v] = (int)flat.size();
+    for (int64_t p = 0; p < npx; p += kFlatChunk) flat.push_back(FlatItem{v, 0, p, std::min(npx, p + kFlatChunk)});
+  }
+  plan->item_begin[n] = (int)items.size();
+  plan->flat_begin[n] = (int)flat.size();
+  if (upload(&plan->d_views, vd) != hipSuccess || upload(&plan->d_items, items) != hipSuccess ||
+      upload(&plan->d_flat, flat) != hipSuccess)
+    return IGSP_ERR_HIP;
+  if (hipMalloc(&plan->d_map, (size_t)std::max<int64_t>(map_elems, 64) * esz) != hipSuccess) return IGSP_ERR_HIP;
+  const size_t hb = (size_t)n * kBins * sizeof(uint32_t), rb = (size_t)n * kRefineBins * sizeof(uint32_t);
+  if (hipMalloc(reinterpret_cast<void**>(&plan->d_hist), hb) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_rhist), rb) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_state), (size_t)n * sizeof(MedState)) != hipSuccess)
+    return IGSP_ERR_HIP;
+  // Histograms start at zero once; every call's selection kernels clear them
+  // again after reading, so later calls need no memset (capturable).
+  if (hipMemset(plan->d_hist, 0, hb) != hipSuccess || hipMemset(plan->d_rhist, 0, rb) != hipSuccess ||
+      hipMemset(plan->d_state, 0, (size_t)n * sizeof(MedState)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess)
+    return IGSP_ERR_HIP;
+  g_edge_plans.push_front(std::move(plan));
+  while ((int)g_edge_plans.size() > kMaxPlans) g_edge_plans.pop_back();
+  *out = g_edge_plans.front();
+  return IGSP_OK;
+}
+
+igsp_status get_edge_plan(const igsp_view* views, int32_t n_views, const igsp_edge_opts* opts,
+                          std::shared_ptr<EdgePlan>* out) {
+  int dev = 0;
+  igsp_status st = check_device(&dev);
+  if (st != IGSP_OK) return st;
+  EdgeKey key;
+  key.device = dev;
+  key.precision = opts ? opts->precision : IGSP_FP32;
+  key.seg_rows = (opts && opts->seg_rows) ? opts->seg_rows : default_seg_rows();
+  key.wg_waves = (opts && opts->wg_waves) ? opts->wg_waves : default_wg_waves();
+  key.views.assign(views, views + n_views);
+  for (auto it = g_edge_plans.begin(); it != g_edge_plans.end(); ++it) {
+    if ((*it)->key == key) {
+      g_edge_plans.splice(g_edge_plans.begin(), g_edge_plans, it);
+      *out = g_edge_plans.front();
+      return IGSP_OK;
+    }
+  }
+  return build_edge_plan(key, out);
+}
+
+igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, float* out_maps,
+                         const igsp_edge_opts* opts, hipStream_t s) {
+  EdgeLaunch L;
+  L.images = images;
+  L.img_end = img_end;
+  L.out = out_maps;
+  L.views = P->d_views;
+  L.items = P->d_items;
+  L.flat = P->d_flat;
+  L.map = P->d_map;
+  L.hist = P->d_hist;
+  L.rhist = P->d_rhist;
+  L.state = P->d_state;
+  L.medians_dn = opts ? opts->medians : nullptr;
+  L.survivors = opts ? opts->survivors : nullptr;
+  L.stage_events = opts ? reinterpret_cast<hipEvent_t*>(opts->stage_events) : nullptr;
+  L.precision = P->key.precision;
+  L.wg_waves = P->key.wg_waves;
+  L.seg_rows = P->key.seg_rows;
+  const bool batched = !opts || opts->batched;
+  const int n = P->n_views;
+  // refinement passes of the median's radix selection: (digit bits) per pass
+  std::vector<int> passes;
+  if (L.precision == IGSP_FP16) passes = {3};
+  else if (L.precision == IGSP_FP32) passes = {8, 8};
+  hipEvent_t* ev = L.stage_events;
+  auto mark = [&](int k, bool on) -> hipError_t {
+    return (ev && on) ? hipEventRecord(ev[k], s) : hipSuccess;
+  };
+  auto run = [&](int v0, int v1, bool marks) -> hipError_t {
+    const int i0 = P->item_begin[v0], i1 = P->item_begin[v1];
+    const int f0 = P->flat_begin[v0], f1 = P->flat_begin[v1];
+    hipError_t e = launch_edge_fused(L, i0, i1 - i0, s);
+    if (e == hipSuccess) e = mark(1, marks);
+    if (e == hipSuccess) e = launch_median_select(L, v0, v1 - v0, s);
+    for (int db : passes) {
+      if (e == hipSuccess) e = launch_median_refine(L, f0, f1 - f0, db, s);
+      if (e == hipSuccess) e = launch_refine_select(L, v0, v1 - v0, db, 0, s);
+    }
+    if (e == hipSuccess) e = mark(2, marks);
+    if (e == hipSuccess) e = launch_normalise(L, f0, f1 - f0, s);
+    if (e == hipSuccess) e = mark(3, marks);
+    return e;
+  };
+  hipError_t e = mark(0, true);
+  if (e == hipSuccess && batched) {
+    e = run(0, n, true);
+  } else if (e == hipSuccess) {
+    for (int v = 0; v < n && e == hipSuccess; ++v) e = run(v, v + 1, false);
+    for (int k = 1; k < 4 && e == hipSuccess; ++k) e = mark(k, true);
+  }
+  return e == hipSuccess ? IGSP_OK : IGSP_ERR_HIP;
+}
+
+// ------------------------------------------------------------------ LAS
+
+struct LasPlan {
+  int device = 0;
+  int n_blocks = 0;
+  int32_t* d_counts = nullptr;
+  int64_t* d_offsets = nullptr;
+  LasScalars* d_scalars = nullptr;
+  ~LasPlan() { (void)hipFree(d_counts); (void)hipFree(d_offsets); (void)hipFree(d_scalars); }
+};
+std::list<std::shared_ptr<LasPlan>> g_las_plans;
+
+igsp_status get_las_plan(int64_t capacity, std::shared_ptr<LasPlan>* out) {
+  int dev = 0;
+  igsp_status st = check_device(&dev);
+  if (st != IGSP_OK) return st;
+  const int nb = (int)std::max<int64_t>(1, (capacity + kLasRows - 1) / kLasRows);
+  for (auto& p : g_las_plans)
+    if (p->device == dev && p->n_blocks == nb) {
+      *out = p;
+      return IGSP_OK;
+    }
+  auto plan = std::make_shared<LasPlan>();
+  plan->device = dev;
+  plan->n_blocks = nb;
+  if (hipMalloc(reinterpret_cast<void**>(&plan->d_counts), nb * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_offsets), nb * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_scalars), sizeof(LasScalars)) != hipSuccess)
+    return IGSP_ERR_HIP;
+  g_las_plans.push_front(std::move(plan));
+  *out = g_las_plans.front();
+  return IGSP_OK;
+}
+
+igsp_status enqueue_las(LasPlan* P, const igsp_gaussians* g, const uint8_t* mask, const igsp_las_out* out,
+                        const igsp_las_params* p, hipStream_t s) {
+  const double a = p ? p->alpha : 0.5, gm = p ? p->gamma : 0.85, b = p ? p->beta : 0.6;
+  LasLaunch L;
+  L.g = *g;
+  L.mask = mask;
+  L.split_idx = out->split_idx;
+  L.status = out->status;
+  L.n_split = out->n_split;
+  L.alpha = (float)a;
+  L.ln_alpha = (float)std::log(a);
+  L.ln_gamma = (float)std::log(gm);
+  L.ln_beta = (float)std::log(b);
+  L.one_minus_beta = (float)(1.0 - b);
+  L.block_counts = P->d_counts;
+  L.block_offsets = P->d_offsets;
+  L.scalars = P->d_scalars;
+  L.n_blocks = P->n_blocks;
+  return launch_las(L, s) == hipSuccess ? IGSP_OK : IGSP_ERR_HIP;
+}
+
+}  // namespace
+}  // namespace igsp
+
+using namespace igsp;
+
+extern "C" int32_t igsp_version(void) { return 1; }
+
+extern "C" igsp_status edge_importance(const uint8_t* images, const igsp_view* views, int32_t n_views,
+                                       float* out_maps, const igsp_edge_opts* opts, void* stream) {
+  EdgeExtent ext{};
+  igsp_status st = validate_edge(images, views, n_views, out_maps, opts, &ext);
+  if (st != IGSP_OK || n_views == 0) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::shared_ptr<EdgePlan> plan;
+  st = get_edge_plan(views, n_views, opts, &plan);
+  if (st != IGSP_OK) return st;
+  return enqueue_edge(plan.get(), images, ext.img_end, out_maps, opts, static_cast<hipStream_t>(stream));
+}
+
+extern "C" igsp_status long_axis_split(const igsp_gaussians* g, const uint8_t* mask, const igsp_las_out* out,
+                                       const igsp_las_params* params, void* stream) {
+  igsp_status st = validate_las(g, mask, out, params);
+  if (st != IGSP_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::shared_ptr<LasPlan> plan;
+  st = get_las_plan(g->capacity, &plan);
+  if (st != IGSP_OK) return st;
+  return enqueue_las(plan.get(), g, mask, out, params, static_cast<hipStream_t>(stream));
+}
+
+struct igsp_step {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::shared_ptr<EdgePlan> edge;  // the graph's kernels use these buffers
+  std::shared_ptr<LasPlan> las;
+};
+
+extern "C" igsp_status igsp_step_create(const uint8_t* images, const igsp_view* views, int32_t n_views,
+                                        float* out_maps, const igsp_edge_opts* opts, const igsp_gaussians* g,
+                                        const uint8_t* mask, const igsp_las_out* out,
+                                        const igsp_las_params* params, void* stream, igsp_step** step) {
+  if (!step) return IGSP_ERR_NULL;
+  *step = nullptr;
+  EdgeExtent ext{};
+  igsp_status st = validate_edge(images, views, n_views, out_maps, opts, &ext);
+  if (st != IGSP_OK) return st;
+  st = validate_las(g, mask, out, params);
+  if (st != IGSP_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::shared_ptr<EdgePlan> eplan;
+  if (n_views > 0) {
+    st = get_edge_plan(views, n_views, opts, &eplan);
+    if (st != IGSP_OK) return st;
+  }
+  std::shared_ptr<LasPlan> lplan;
+  st = get_las_plan(g->capacity, &lplan);
+  if (st != IGSP_OK) return st;
+  hipStream_t cs = static_cast<hipStream_t>(stream);
+  hipStream_t own = nullptr;
+  if (!cs) {  // the null stream cannot be captured
+    if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) return IGSP_ERR_HIP;
+    cs = own;
+  }
+  igsp_edge_opts eo = opts ? *opts : igsp_edge_opts{IGSP_FP32, 1, 0, 0, nullptr, nullptr, nullptr};
+  eo.stage_events = nullptr;  // no event records inside a graph
+  opts = &eo;
+  auto s = std::make_unique<igsp_step>();
+  igsp_status rs = IGSP_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rs = IGSP_ERR_HIP;
+  } else {
+    if (eplan) rs = enqueue_edge(eplan.get(), images, ext.img_end, out_maps, opts, cs);
+    if (rs == IGSP_OK) rs = enqueue_las(lplan.get(), g, mask, out, params, cs);
+    hipError_t e = hipStreamEndCapture(cs, &s->graph);
+    if (rs == IGSP_OK && e != hipSuccess) rs = IGSP_ERR_HIP;
+    if (rs == IGSP_OK && hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0) != hipSuccess)
+      rs = IGSP_ERR_HIP;
+  }
+  if (own) (void)hipStreamDestroy(own);
+  if (rs != IGSP_OK) {
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    return rs;
+  }
+  s->edge = eplan;
+  s->las = lplan;
+  *step = s.release();
+  return IGSP_OK;
+}
+
+extern "C" igsp_status igsp_step_launch(igsp_step* step, void* stream) {
+  if (!step || !step->exec) return IGSP_ERR_NULL;
+  return hipGraphLaunch(step->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? IGSP_OK : IGSP_ERR_HIP;
+}
+
+extern "C" void igsp_step_destroy(igsp_step* step) {
+  if (!step) return;
+  if (step->exec) (void)hipGraphExecDestroy(step->exec);
+  if (step->graph) (void)hipGraphDestroy(step->graph);
+  delete step;
+}
+
+extern "C" void igsp_release_plans(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_edge_plans.clear();
+  g_las_plans.clear();
+}

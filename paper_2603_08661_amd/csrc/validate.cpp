@@ -1,0 +1,77 @@
+// Host-side argument validation of the C ABI. Pure C++ with no HIP calls, so
+// every error path can be exercised on a machine without a GPU; a call that
+// fails here enqueues nothing.
+#include "validate.h"
+
+#include <cmath>
+
+namespace igsp {
+
+static bool unit_interval(float v) { return v > 0.0f && v <= 1.0f; }  // NaN fails both
+
+igsp_status validate_edge(const uint8_t* images, const igsp_view* views, int32_t n_views, const float* out,
+                          const igsp_edge_opts* opts, EdgeExtent* ext) {
+  if (n_views < 0) return IGSP_ERR_DIMS;
+  if (n_views == 0) return IGSP_OK;
+  if (!images || !views || !out) return IGSP_ERR_NULL;
+  if ((reinterpret_cast<uintptr_t>(images) & 15u) != 0) return IGSP_ERR_ALIGN;
+  if (opts) {
+    if (opts->precision < IGSP_FP32 || opts->precision > IGSP_BF16) return IGSP_ERR_PARAM;
+    if (opts->batched != 0 && opts->batched != 1) return IGSP_ERR_PARAM;
+    if (opts->seg_rows != 0 && (opts->seg_rows < 8 || opts->seg_rows > 4096)) return IGSP_ERR_PARAM;
+    const int w = opts->wg_waves;
+    if (w != 0 && w != 1 && w != 2 && w != 4 && w != 8) return IGSP_ERR_PARAM;
+  }
+  int64_t in_end = 0, out_end = 0, px = 0;
+  for (int32_t v = 0; v < n_views; ++v) {
+    const igsp_view& d = views[v];
+    if (d.width < 3 || d.height < 3) return IGSP_ERR_DIMS;
+    const int64_t npx = (int64_t)d.width * d.height;
+    if (npx >= (int64_t(1) << 31)) return IGSP_ERR_DIMS;
+    if (d.in_offset < 0 || d.out_offset < 0) return IGSP_ERR_DIMS;
+    if (d.in_offset > (int64_t(1) << 60) || d.out_offset > (int64_t(1) << 60)) return IGSP_ERR_DIMS;
+    const int64_t ie = d.in_offset + 3 * npx, oe = d.out_offset + npx;
+    if (ie > in_end) in_end = ie;
+    if (oe > out_end) out_end = oe;
+    px += npx;
+  }
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(images), a1 = a0 + (uintptr_t)in_end;
+  const uintptr_t b0 = reinterpret_cast<uintptr_t>(out), b1 = b0 + (uintptr_t)out_end * sizeof(float);
+  if (a0 < b1 && b0 < a1) return IGSP_ERR_OVERLAP;
+  if (ext) {
+    ext->img_end = in_end;
+    ext->out_end = out_end;
+    ext->pixels = px;
+  }
+  return IGSP_OK;
+}
+
+igsp_status validate_las(const igsp_gaussians* g, const uint8_t* mask, const igsp_las_out* out,
+                         const igsp_las_params* p) {
+  if (!g || !mask || !out) return IGSP_ERR_NULL;
+  if (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->count) return IGSP_ERR_NULL;
+  if (!out->split_idx || !out->status) return IGSP_ERR_NULL;
+  if (g->feat_dim < 0) return IGSP_ERR_PARAM;
+  if (g->feat_dim > 0 && !g->features) return IGSP_ERR_NULL;
+  if (g->capacity < 0 || g->capacity >= (int64_t(1) << 31)) return IGSP_ERR_DIMS;
+  if (p && (!unit_interval(p->alpha) || !unit_interval(p->gamma) || !unit_interval(p->beta)))
+    return IGSP_ERR_PARAM;
+  return IGSP_OK;
+}
+
+}  // namespace igsp
+
+extern "C" const char* igsp_status_string(int32_t status) {
+  switch (status) {
+    case IGSP_OK: return "ok";
+    case IGSP_ERR_NULL: return "a required pointer is NULL";
+    case IGSP_ERR_DIMS: return "invalid dimensions, offsets or counts";
+    case IGSP_ERR_ALIGN: return "images must be 16-byte aligned";
+    case IGSP_ERR_OVERLAP: return "input and output ranges overlap";
+    case IGSP_ERR_PARAM: return "invalid parameter";
+    case IGSP_ERR_CAPACITY: return "capacity exceeded: nothing was split";
+    case IGSP_ERR_HIP: return "HIP runtime error";
+    case IGSP_ERR_UNSUPPORTED: return "unsupported device (gfx950 required)";
+    default: return "unknown status";
+  }
+}

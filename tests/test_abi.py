@@ -1,0 +1,128 @@
+"""C ABI on the host (no GPU): the library loads, exports every symbol the
+header declares, and rejects invalid arguments with the documented status
+before touching the GPU. Pointers below are never dereferenced: validation
+only compares their values."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2603_08661_amd as igsp
+from paper_2603_08661_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "igsp.h")
+
+FAKE_IMG = 0x7F0000000000          # 16-byte aligned, never dereferenced
+FAKE_OUT = 0x7F1000000000
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\*?\s+\*?([a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+def test_exports_every_declared_symbol():
+    L = igsp.lib()
+    names = declared_functions()
+    assert set(names) == set(B.EXPORTS), names
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.igsp_version() == 1
+
+
+def test_status_strings():
+    for code in B.STATUS:
+        assert igsp.status_string(code)
+    assert "capacity" in igsp.status_string(-6)
+
+
+def edge(views, n=None, images=FAKE_IMG, out=FAKE_OUT, opts=None):
+    arr = (B.View * max(len(views), 1))(*[B.View(*v) for v in views])
+    n = len(views) if n is None else n
+    o = ctypes.byref(opts) if opts is not None else None
+    return igsp.lib().edge_importance(images, arr, n, out, o, None)
+
+
+GOOD = [(16, 8, 0, 0), (5, 3, 16 * 8 * 3, 16 * 8)]
+
+
+@pytest.mark.parametrize("views,n,kw,code", [
+    (GOOD, -1, {}, -2),
+    (GOOD, 0, {"images": 0, "out": 0}, 0),           # n = 0: no-op even with NULLs
+    (GOOD, None, {"images": 0}, -1),
+    (GOOD, None, {"out": 0}, -1),
+    (GOOD, None, {"images": FAKE_IMG + 3}, -3),
+    ([(2, 8, 0, 0)], None, {}, -2),
+    ([(8, 2, 0, 0)], None, {}, -2),
+    ([(65536, 32768, 0, 0)], None, {}, -2),            # W*H = 2^31
+    ([(8, 8, -1, 0)], None, {}, -2),
+    ([(8, 8, 0, -5)], None, {}, -2),
+    ([(16, 16, 0, 0)], None, {"out": FAKE_IMG + 100}, -4),
+    ([(16, 16, 0, 0)], None, {"out": FAKE_IMG - 4 * 256 + 4}, -4),
+])
+def test_edge_validation(views, n, kw, code):
+    assert edge(views, n, **kw) == code
+
+
+@pytest.mark.parametrize("field,val", [("precision", 3), ("precision", -1), ("batched", 2), ("seg_rows", 4),
+                                       ("seg_rows", 5000), ("wg_waves", 3), ("wg_waves", 16)])
+def test_edge_bad_options(field, val):
+    o = B.EdgeOpts(0, 1, 0, 0, None, None, None)
+    setattr(o, field, val)
+    assert edge(GOOD, opts=o) == -5
+
+
+def las(g=None, mask=0x1000, out=None, prm=None):
+    g = g or B.Gaussians(0x10, 0x20, 0x30, 0x40, None, 0, 0x50, 100)
+    out = out or B.LasOut(0x60, 0x70, None)
+    L = igsp.lib()
+    return L.long_axis_split(ctypes.byref(g) if g else None, mask, ctypes.byref(out),
+                             ctypes.byref(prm) if prm else None, None)
+
+
+def test_las_validation():
+    L = igsp.lib()
+    assert L.long_axis_split(None, 0x1000, None, None, None) == -1
+    assert las(mask=0) == -1
+    for k in ("means", "log_scales", "quats", "opacity_logits", "count"):
+        g = B.Gaussians(0x10, 0x20, 0x30, 0x40, None, 0, 0x50, 100)
+        setattr(g, k, 0)
+        assert las(g=g) == -1, k
+    assert las(out=B.LasOut(0, 0x70, None)) == -1
+    assert las(out=B.LasOut(0x60, 0, None)) == -1
+    assert las(g=B.Gaussians(0x10, 0x20, 0x30, 0x40, None, -1, 0x50, 100)) == -5
+    assert las(g=B.Gaussians(0x10, 0x20, 0x30, 0x40, None, 4, 0x50, 100)) == -1   # feat_dim > 0, NULL features
+    assert las(g=B.Gaussians(0x10, 0x20, 0x30, 0x40, None, 0, 0x50, -1)) == -2
+    assert las(g=B.Gaussians(0x10, 0x20, 0x30, 0x40, None, 0, 0x50, 2 ** 31)) == -2
+    for a, gm, b in ((0.0, 0.85, 0.6), (0.5, 1.5, 0.6), (0.5, 0.85, -0.1), (math.nan, 0.85, 0.6),
+                     (0.5, 0.85, math.inf)):
+        assert las(prm=B.LasParams(a, gm, b)) == -5
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/libigsp.so")
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(ImportError):
+        B.lib()
+
+
+def test_product_path_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2603_08661_amd")
+    for dp, _, fs in os.walk(pkg):
+        for f in fs:
+            if f.endswith((".py", ".hip", ".cpp", ".h", ".c")) or f == "Makefile":
+                txt = open(os.path.join(dp, f)).read()
+                assert not re.search(r"\boracle\b|igsp_oracle|liboracle", txt), f
+
+
+def test_view_struct_layout_matches_header():
+    assert ctypes.sizeof(B.View) == 24
+    assert ctypes.sizeof(B.EdgeOpts) == 40
+    assert ctypes.sizeof(B.Gaussians) == 64
+    assert ctypes.sizeof(B.LasOut) == 24
+    assert np.dtype([("w", "<i4"), ("h", "<i4"), ("i", "<i8"), ("o", "<i8")]).itemsize == 24

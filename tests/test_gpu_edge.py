@@ -1,0 +1,122 @@
+"""GPU parity of edge_importance against the CPU oracle (through the C ABI).
+
+Sizes the oracle finishes in seconds that still span several strips (248
+output columns each), several bands and ragged tails, plus full-size batched
+workloads checked on sampled views in the launch configuration the benchmark
+times.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import check_batch, compare_view, gpu_edge, view_map
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "fp16", "bf16"]
+
+
+def small_batch(in_align=1, out_align=1):
+    """Ragged views around every strip/band/alignment boundary."""
+    sizes = [(3, 3), (4, 5), (7, 3), (3, 9), (247, 9), (248, 17), (249, 31), (252, 8), (253, 12),
+             (256, 64), (257, 300), (500, 70), (744, 33), (1001, 13), (61, 513)]
+    imgs = [synth.image(40 + k, w, h, n_poly=6, texture=(k % 2 == 0)) for k, (w, h) in enumerate(sizes)]
+    return synth.pack_views(imgs, in_align=in_align, out_align=out_align)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_workload1_single_view(precision):
+    w = synth.workload(1)
+    vb = w.render(in_align=256, out_align=64)
+    for batched in (True, False):
+        st = check_batch(vb, precision, batched)
+        print(precision, batched, st)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_ragged_views_unaligned(precision):
+    vb = small_batch()
+    st = check_batch(vb, precision, True)
+    print(precision, sum(s["mismatch"] for s in st), max(s["scaled_err"] for s in st))
+
+
+@pytest.mark.parametrize("seg_rows,wg_waves", [(8, 1), (16, 2), (32, 4), (64, 8), (128, 4), (24, 2)])
+def test_tile_shapes(seg_rows, wg_waves):
+    vb = small_batch(in_align=16, out_align=4)
+    check_batch(vb, "fp32", True, seg_rows=seg_rows, wg_waves=wg_waves)
+
+
+def test_adversarial_images():
+    H, W = 40, 300
+    imgs = []
+    im = np.zeros((H, W, 3), np.uint8)
+    imgs.append(im.copy())                                   # constant: nothing survives
+    im[:, 150:] = 255
+    imgs.append(im.copy())                                   # ideal step
+    imgs.append(np.ascontiguousarray(np.transpose(imgs[-1][:, :H], (1, 0, 2))))
+    ramp = np.zeros((H, W, 3), np.uint8)
+    ramp[:] = (np.arange(W) % 256).astype(np.uint8)[None, :, None]
+    imgs.append(ramp)
+    yy, xx = np.mgrid[0:H, 0:W]
+    imgs.append(np.repeat((((yy // 2 + xx // 3) % 2) * 200 + 20).astype(np.uint8)[..., None], 3, 2))
+    imgs.append(np.random.default_rng(0).integers(0, 256, (H, W, 3), dtype=np.uint8))
+    imgs.append(np.random.default_rng(1).integers(100, 103, (H, W, 3), dtype=np.uint8))
+    vb = synth.pack_views(imgs, in_align=1, out_align=1)
+    for p in PRECS:
+        check_batch(vb, p, True)
+
+
+def test_step_edge_ridge_exact():
+    im = np.zeros((37, 520, 3), np.uint8)
+    im[:, 261:] = 255
+    vb = synth.pack_views([im])
+    E, _, nsv = gpu_edge(vb, "fp32")
+    Em = view_map(E, vb, 0)
+    assert (Em[:, 260] == 1.0).all() and (np.delete(Em, 260, axis=1) == 0).all() and nsv[0] == 37
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_batched_equals_plain_and_deterministic(precision):
+    vb = small_batch(in_align=16, out_align=4)
+    a = gpu_edge(vb, precision, True)
+    b = gpu_edge(vb, precision, False)
+    c = gpu_edge(vb, precision, True, reps=3)       # repeated calls reuse the plan
+    for x, y in ((a, b), (a, c)):
+        for u, v in zip(x, y):
+            assert (u == v).all()
+
+
+def test_permuting_views_permutes_outputs():
+    vb = small_batch(in_align=16, out_align=4)
+    perm = list(range(vb.n))[::-1]
+    vp = synth.pack_views([vb.view(v) for v in perm], in_align=7, out_align=3)
+    a, _, _ = gpu_edge(vb, "fp16")
+    b, _, _ = gpu_edge(vp, "fp16")
+    for k, v in enumerate(perm):
+        assert (view_map(a, vb, v) == view_map(b, vp, k)).all()
+
+
+def test_workload2_full_oracle():
+    w = synth.workload(2)
+    vb = w.render(in_align=256, out_align=64)
+    for p in PRECS:
+        st = check_batch(vb, p, p != "fp32")
+        print("workload2", p, st)
+
+
+@pytest.mark.parametrize("c,precisions,sample", [(3, ["fp16", "fp32"], [0, 57, 199]),
+                                                 (4, ["fp16", "bf16"], [0, 1, 148, 149]),
+                                                 (5, ["bf16"], [0, 150, 299])])
+def test_full_size_workloads_sampled(c, precisions, sample):
+    """Every view of the full workload goes through one batched launch per
+    stage; sampled views are checked against the oracle pixel by pixel."""
+    w = synth.workload(c)
+    vb = w.render()
+    for p in precisions:
+        E, med, nsv = gpu_edge(vb, p, True)
+        for v in sample:
+            ref = oracle.edge_view(vb.view(v))
+            st = compare_view(view_map(E, vb, v), ref, p, med[v], nsv[v])
+            print(f"workload{c} {p} view {v}", st)
+        assert (nsv > 0).all() and (med > 0).all()
