@@ -151,8 +151,11 @@ def edge_opts(precision="fp32", batched=True, seg_rows=0, wg_waves=0, medians=No
     _need(survivors, torch.int32, "survivors")
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     ev = None
-    if stage_events is not None:   # 4 torch.cuda.Event (created with enable_timing=True)
-        arr = (ctypes.c_void_p * 4)(*[int(e.cuda_event) for e in stage_events])
+    if stage_events is not None:   # 4 torch.cuda.Event, each recorded once already
+        handles = [int(e.cuda_event) for e in stage_events]
+        if len(handles) != 4 or not all(handles):
+            raise ValueError("stage_events: four torch.cuda.Event that have been recorded at least once")
+        arr = (ctypes.c_void_p * 4)(*handles)
         ev = ctypes.cast(arr, ctypes.c_void_p)
         _EVENT_KEEPALIVE.append(arr)
         del _EVENT_KEEPALIVE[:-8]

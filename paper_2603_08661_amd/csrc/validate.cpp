@@ -21,6 +21,9 @@ igsp_status validate_edge(const uint8_t* images, const igsp_view* views, int32_t
     if (opts->seg_rows != 0 && (opts->seg_rows < 8 || opts->seg_rows > 4096)) return IGSP_ERR_PARAM;
     const int w = opts->wg_waves;
     if (w != 0 && w != 1 && w != 2 && w != 4 && w != 8) return IGSP_ERR_PARAM;
+    if (opts->stage_events)
+      for (int k = 0; k < 4; ++k)
+        if (!opts->stage_events[k]) return IGSP_ERR_NULL;
   }
   int64_t in_end = 0, out_end = 0, px = 0;
   for (int32_t v = 0; v < n_views; ++v) {

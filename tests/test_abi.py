@@ -126,3 +126,9 @@ def test_view_struct_layout_matches_header():
     assert ctypes.sizeof(B.Gaussians) == 64
     assert ctypes.sizeof(B.LasOut) == 24
     assert np.dtype([("w", "<i4"), ("h", "<i4"), ("i", "<i8"), ("o", "<i8")]).itemsize == 24
+
+
+def test_null_stage_event_rejected():
+    ev = (ctypes.c_void_p * 4)(1, 2, None, 4)
+    o = B.EdgeOpts(0, 1, 0, 0, None, None, ctypes.cast(ev, ctypes.c_void_p))
+    assert edge(GOOD, opts=o) == -1
