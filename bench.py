@@ -41,6 +41,43 @@ def percentile_ms(events_pairs):
     return float(np.mean([a.elapsed_time(b) for a, b in events_pairs]))
 
 
+def copy_calibration(nbytes: int):
+    """A plain copy of known size: reads and writes nbytes per launch, so the
+    HBM counters of its dispatches calibrate FETCH_SIZE and WRITE_SIZE."""
+    import torch
+
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+
+
+def traffic_from_profile(kernel: str, prec: str, workload: str, seg_rows: int, wg_waves: int):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when that summary was taken on another kernel source,
+    workload, storage precision or tile shape."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_2603_08661_amd", "csrc", "edge_kernels.hip")
+    try:
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if (kv.get("kernel_source_sha256") != digest or kv.get("precision") != prec
+                or kv.get("workload") != workload or kv.get("tile") != f"{seg_rows}x{wg_waves}"):
+            return None
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,7 +91,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     ap.add_argument("--stage-reps", type=int, default=10)
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default tile shape")
+    ap.add_argument("--form", default="batched", choices=["batched", "staged", "persistent"],
+                    help="batched launch form (batched: autotuned between staged and persistent)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes three times (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
                                    "(views would shard with no exchange, see the design notes)",
@@ -98,10 +143,9 @@ def main():
     torch.cuda.synchronize()
 
     stream = torch.cuda.Stream()
-    batched = w.batched or args.workload == 5
 
-    def edge(p, b, ev=None):
-        igsp.edge_importance(img, views, out, precision=p, batched=b, seg_rows=args.seg_rows,
+    def edge(p, ev=None):
+        igsp.edge_importance(img, views, out, precision=p, batched=bform, seg_rows=args.seg_rows,
                              wg_waves=args.wg_waves, stage_events=ev, stream=stream)
 
     def las():
@@ -122,19 +166,33 @@ def main():
         wall = (time.perf_counter() - w0) * 1e3 / reps
         return e0.elapsed_time(e1) / reps, wall
 
+    # ---- launch form and tile shape: explicit, the library default, or
+    #      autotuned on this batch
+    seg, wgw, bform = args.seg_rows, args.wg_waves, args.form
+    if seg == 0 and wgw == 0 and not args.no_tune:
+        t1 = time.time()
+        seg, wgw, bform = igsp.edge_autotune(img, views, out, precision=prec, batched=args.form, stream=stream)
+        torch.cuda.synchronize()
+        log(f"autotuned: form={bform} seg_rows={seg} wg_waves={wgw} ({time.time() - t1:.2f}s)")
+    elif seg == 0 and wgw == 0:
+        seg, wgw = 64, 4
+    if bform == "batched":
+        bform = "persistent"
+    args.seg_rows, args.wg_waves = seg, wgw
+
     # ---- primary form: batched, reduced-precision storage, graph-captured step
     if w.graph:
         with torch.cuda.stream(stream):
-            step = igsp.Step(img, views, out, G, mask, sidx, status, precision=prec, batched=True,
+            step = igsp.Step(img, views, out, G, mask, sidx, status, precision=prec, batched=bform,
                              seg_rows=args.seg_rows, wg_waves=args.wg_waves, stream=stream)
         run_primary = lambda: step.launch(stream)  # noqa: E731
-        form = f"batched {prec} + LAS, one HIP graph per step"
+        form = f"batched ({bform}) {prec} + LAS, one HIP graph per step"
     else:
         def run_primary():
-            edge(prec, batched)
+            edge(prec)
             if has_las:
                 las()
-        form = f"{'batched' if batched else 'plain per-view'} {prec}" + (" + LAS" if has_las else "")
+        form = f"batched ({bform}) {prec}" + (" + LAS" if has_las else "")
     ms, wall = timed(run_primary, args.warmup, args.steps)
     log(f"primary ({form}): {ms:.3f} ms/step (wall {wall:.3f})")
     if has_las:
@@ -146,7 +204,7 @@ def main():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         for e in ev:            # torch creates the HIP event on its first record
             e.record(stream)
-        edge(prec, True, ev)
+        edge(prec, ev)
         torch.cuda.synchronize()
         pairs["fused"].append((ev[0], ev[1]))
         pairs["select"].append((ev[1], ev[2]))
@@ -157,7 +215,11 @@ def main():
     if has_las:
         las_ms, _ = timed(las, 1, args.stage_reps)
     sb = STORE_BYTES[prec]
-    fused_bytes = vb.pixels * (3 + sb)
+    if bform == "persistent":     # one kernel: RGB in, maps out
+        kernel, per_px = "edge_persistent", 7
+    else:                         # the stencil kernel: RGB in, stored survivors out
+        kernel, per_px = "edge_fused", 3 + sb
+    fused_bytes = vb.pixels * per_px
     achieved = fused_bytes / (stage_ms["fused"] * 1e-3) / 1e9
     log(f"stages: {stage_ms}, las {las_ms}")
 
@@ -165,7 +227,7 @@ def main():
     plain = None
     if not args.no_plain:
         def run_plain():
-            edge("fp32", False)
+            igsp.edge_importance(img, views, out, precision="fp32", batched=False, stream=stream)
             if has_las:
                 las()
         pms, pwall = timed(run_plain, 1, max(1, min(args.steps, 5)))
@@ -226,12 +288,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "views": vb.n, "megapixels": round(mpx, 2),
                    "intermediate": prec, "form": form, "gaussians": w.n_gauss, "split": w.n_split,
+                   "tile": f"{seg}x{wgw}",
                    "arithmetic": "int32 exact through Sobel, fp32 magnitude/suppression/median/LAS"},
         "wall_ms_per_step": round(wall, 4),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "roofline": {"bound": "hbm", "kernel": "edge_fused", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "algorithmic_bytes_per_px": 3 + sb,
+                     "traffic": traffic_from_profile(kernel, prec, w.name, seg, wgw),
+                     "algorithmic_bytes_per_px": per_px,
                      "bytes_per_launch": int(fused_bytes)},
         "edge_pipeline": {"ms": round(stage_ms["edge"], 4),
                           "mpx_per_s": round(mpx / (stage_ms["edge"] * 1e-3), 1),

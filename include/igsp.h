@@ -75,11 +75,20 @@ typedef struct {
    after it in every mode; maps are float32 in every mode. */
 typedef enum { IGSP_FP32 = 0, IGSP_FP16 = 1, IGSP_BF16 = 2 } igsp_precision;
 
+/* Launch form of edge_importance. All forms compute identical maps. */
+typedef enum {
+  IGSP_PLAIN = 0,               /* each view by its own sequence of launches  */
+  IGSP_BATCHED = 1,             /* every view together; the library picks the
+                                   form below (tuned, else staged)            */
+  IGSP_BATCHED_STAGED = 2,      /* every view in one launch per stage         */
+  IGSP_BATCHED_PERSISTENT = 3   /* every view and stage in one persistent
+                                   launch; later stages of earlier views run
+                                   beside the stencil pass of later ones      */
+} igsp_form;
+
 typedef struct {
   int32_t precision;     /* igsp_precision                                    */
-  int32_t batched;       /* 1: every view in one launch per stage (default);
-                            0: the plain form, each view processed by its own
-                            sequence of launches                              */
+  int32_t batched;       /* igsp_form                                         */
   int32_t seg_rows;      /* output rows per wavefront segment; 0 = tuned      */
   int32_t wg_waves;      /* wavefronts per work-group (1, 2, 4, 8); 0 = tuned */
   float* medians;        /* (device, optional) [n_views]: the median surviving
@@ -88,10 +97,11 @@ typedef struct {
   int32_t* survivors;    /* (device, optional) [n_views]: surviving pixels    */
   void** stage_events;   /* (host, optional) 4 hipEvent_t recorded on `stream`
                             before the stencil pass, after it, after the median
-                            selection and after the normalisation (batched
-                            form; the plain form records the last three after
-                            its final view). Profiling only: no work changes.
-                            Ignored by igsp_step_create.                       */
+                            selection and after the normalisation (staged
+                            form; the plain and persistent forms record the
+                            last three after their final launch). Profiling
+                            only: no work changes. Ignored by
+                            igsp_step_create.                                  */
 } igsp_edge_opts;
 
 /*
@@ -115,6 +125,27 @@ typedef struct {
  */
 igsp_status edge_importance(const uint8_t* images, const igsp_view* views, int32_t n_views,
                             float* out_maps, const igsp_edge_opts* opts, void* stream);
+
+/*
+ * Autotune the tile shape (rows per wavefront segment x wavefronts per
+ * work-group, i.e. waves per CU through the work-groups resident per CU) and,
+ * for IGSP_BATCHED, the launch form, for these views and this storage
+ * precision: every candidate is run on the given data (out_maps is
+ * overwritten) and timed with HIP events on `stream`. The fastest is
+ * remembered for calls with the same `batched` value whose opts leave
+ * seg_rows and wg_waves at 0 and whose geometry falls in the same size class
+ * (device, precision, total pixels and mean width rounded to powers of two).
+ * If the environment variable IGSP_TUNE_CACHE names a file, tuned entries are
+ * loaded from it on first use and the file is rewritten after tuning (one
+ * JSON object per line).
+ * batched  igsp_form requested by later calls.
+ * best     (host, out, optional) receives the choice: seg_rows, wg_waves and
+ *          in `batched` the concrete form.
+ * Synchronises `stream`; allocates (it creates plans), so never capture it.
+ */
+igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view* views, int32_t n_views,
+                               float* out_maps, int32_t precision, int32_t batched,
+                               igsp_edge_opts* best, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Long-Axis-Split (Sec. 2.2, Algorithms 1 and 2)                            */

@@ -12,6 +12,7 @@ Two operations, both hand-written HIP behind the C ABI of include/igsp.h:
 plus ``Step``, one densification step recorded as a HIP graph.
 """
 from ._binding import (  # noqa: F401
-    BF16, EXPORTS, FP16, FP32, LIB_PATH, PRECISIONS, IgspError, Step, edge_importance, lib,
-    long_axis_split, release_plans, status_string, view_table,
+    BATCHED, BATCHED_PERSISTENT, BATCHED_STAGED, BF16, EXPORTS, FORMS, FP16, FP32, LIB_PATH, PLAIN, PRECISIONS,
+    IgspError, Step, edge_autotune, edge_importance, form_code, lib, long_axis_split, release_plans, status_string,
+    view_table,
 )

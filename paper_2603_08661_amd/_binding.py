@@ -25,7 +25,7 @@ STATUS = {
 }
 
 # Every symbol include/igsp.h declares.
-EXPORTS = ("edge_importance", "long_axis_split", "igsp_step_create", "igsp_step_launch",
+EXPORTS = ("edge_importance", "long_axis_split", "igsp_edge_autotune", "igsp_step_create", "igsp_step_launch",
            "igsp_step_destroy", "igsp_status_string", "igsp_release_plans", "igsp_version")
 
 
@@ -82,6 +82,8 @@ def lib():
         L.long_axis_split.argtypes = [ctypes.POINTER(Gaussians), vp, ctypes.POINTER(LasOut),
                                       ctypes.POINTER(LasParams), vp]
         L.long_axis_split.restype = i32
+        L.igsp_edge_autotune.argtypes = [vp, ctypes.POINTER(View), i32, vp, i32, i32, ctypes.POINTER(EdgeOpts), vp]
+        L.igsp_edge_autotune.restype = i32
         L.igsp_step_create.argtypes = [vp, ctypes.POINTER(View), i32, vp, ctypes.POINTER(EdgeOpts),
                                        ctypes.POINTER(Gaussians), vp, ctypes.POINTER(LasOut),
                                        ctypes.POINTER(LasParams), vp, ctypes.POINTER(vp)]
@@ -143,6 +145,21 @@ def _need(t, dtype, name):
     _ = torch
 
 
+PLAIN, BATCHED, BATCHED_STAGED, BATCHED_PERSISTENT = 0, 1, 2, 3
+FORMS = {"plain": PLAIN, "batched": BATCHED, "staged": BATCHED_STAGED, "persistent": BATCHED_PERSISTENT}
+FORM_NAMES = {v: k for k, v in FORMS.items()}
+
+
+def form_code(batched) -> int:
+    """Launch form: True / "batched" (library's choice), False / "plain",
+    "staged", "persistent", or the integer code."""
+    if isinstance(batched, str):
+        return FORMS[batched]
+    if isinstance(batched, bool):
+        return BATCHED if batched else PLAIN
+    return int(batched)
+
+
 def edge_opts(precision="fp32", batched=True, seg_rows=0, wg_waves=0, medians=None, survivors=None,
               stage_events=None):
     import torch
@@ -159,7 +176,7 @@ def edge_opts(precision="fp32", batched=True, seg_rows=0, wg_waves=0, medians=No
         ev = ctypes.cast(arr, ctypes.c_void_p)
         _EVENT_KEEPALIVE.append(arr)
         del _EVENT_KEEPALIVE[:-8]
-    return EdgeOpts(p, int(bool(batched)), int(seg_rows), int(wg_waves), _ptr(medians), _ptr(survivors), ev)
+    return EdgeOpts(p, form_code(batched), int(seg_rows), int(wg_waves), _ptr(medians), _ptr(survivors), ev)
 
 
 _EVENT_KEEPALIVE: list = []
@@ -197,6 +214,27 @@ def _check_extents(tab, n, images, out_maps, medians=None, survivors=None):
     for t, nm in ((medians, "medians"), (survivors, "survivors")):
         if t is not None and t.numel() < n:
             raise ValueError(f"{nm} needs {n} entries")
+
+
+def edge_autotune(images, views, out_maps, precision="fp32", batched=True, stream=None):
+    """Tune the tile shape (and, for batched=True, the launch form) on these
+    views; returns (seg_rows, wg_waves, form name).
+
+    Later calls with the same ``batched`` and default tile options use the
+    result for geometries of the same size class (and IGSP_TUNE_CACHE, if set,
+    keeps it across runs).
+    """
+    import torch
+
+    _need(images, torch.uint8, "images")
+    _need(out_maps, torch.float32, "out_maps")
+    tab, n = view_table(*views)
+    _check_extents(tab, n, images, out_maps)
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    best = EdgeOpts()
+    _check(lib().igsp_edge_autotune(_ptr(images), tab, n, _ptr(out_maps), p, form_code(batched),
+                                    ctypes.byref(best), _stream(stream)), "igsp_edge_autotune")
+    return int(best.seg_rows), int(best.wg_waves), FORM_NAMES[int(best.batched)]
 
 
 def gaussians_struct(means, log_scales, quats, opacity_logits, count, features=None):

@@ -2,19 +2,23 @@
 //
 // Stage 1, edge_fused: one pass over the 8-bit RGB input computes grayscale,
 // the binomial 5x5 blur, the Sobel gradient, the orientation bin and the
-// non-maximum suppression, writes the surviving magnitudes (FP32, FP16 or
-// BF16 storage) and accumulates a per-view histogram of their top 16 bits.
-// The paper runs these as separate kernels with HBM intermediates and names
-// a shared-memory fusion as future work; here nothing between the bytes and
-// the suppressed magnitude leaves the register file.
+// non-maximum suppression, writes one stored value per surviving pixel
+// (FP32, FP16 or BF16) and accumulates a per-view histogram of its top 16
+// bits. The paper runs these steps as separate kernels with HBM
+// intermediates and names a shared-memory fusion as future work; here
+// nothing between the input bytes and the suppressed magnitude leaves the
+// register file.
 //
 //   - A wavefront owns a vertical strip of 256 input columns (64 lanes x 4
 //     adjacent pixels) and marches down its rows. Vertical taps live in
 //     register sliding windows; horizontal neighbours cross lanes with DPP
-//     wave shifts (one VALU modifier per value), never through LDS.
-//   - Rows are not 4-byte aligned (pitch 3*W), so each row span is fetched as
-//     aligned 16-byte chunks into a per-wave LDS buffer, prefetched one row
-//     ahead, and every lane extracts its 12 bytes with byte-align shifts.
+//     wave shifts, never through LDS.
+//   - Each lane reads its 12 bytes of a row with one unaligned 96-bit buffer
+//     load, one row ahead of its use; a wave's loads cover 768 contiguous
+//     bytes. Row indices, descriptors and bounds are wave-uniform scalar
+//     work, and the loop body issues the same memory operations on every
+//     lane (stores of non-output pixels go past the descriptor's end and are
+//     dropped), so waits never drain the prefetch.
 //   - Gray, blur and Sobel run in exact 32-bit integers (|gx|,|gy| < 2^28).
 //     The magnitude, its orientation test and the suppression comparisons
 //     are FP32.
@@ -22,14 +26,36 @@
 // Stage 2, median_select / median_refine / refine_select: exact radix
 // selection of the lower median of each view's stored survivor values; BF16
 // needs no refinement, FP16 one 3-bit pass, FP32 two 8-bit passes.
-// Stage 3, normalise: map = stored / median at survivors, 0 elsewhere.
+// Stage 3, normalise: map = q / median (FP16) or sqrt(q / median) (FP32,
+// BF16) at survivors, 0 elsewhere.
 
 #include <hip/hip_fp16.h>
 
 #include "igsp_internal.h"
 
+#ifndef IGSP_FUSED_WAVES_PER_EU
+#define IGSP_FUSED_WAVES_PER_EU 4
+#endif
+
 namespace igsp {
 namespace {
+
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+template <class T>
+__device__ __forceinline__ gptr<const T> as_global(const T* p) {
+  return (gptr<const T>)p;
+}
 
 // ------------------------------------------------------------- cross-lane
 
@@ -40,12 +66,12 @@ namespace {
 // wrong values at run time on gfx950 in this toolchain, while the plain
 // v_mov_b32_dpp form is exact.
 __device__ __forceinline__ int from_left(int v) {
-  int r = __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+  int r = __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
   asm volatile("" : "+v"(r));
   return r;
 }
 __device__ __forceinline__ int from_right(int v) {
-  int r = __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
+  int r = __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true);
   asm volatile("" : "+v"(r));
   return r;
 }
@@ -61,36 +87,48 @@ __device__ __forceinline__ int fold(int i, int n) {
   if (i < 0) i += P;
   return i < n ? i : P - i;
 }
+// The same map for an overshoot of at most 4 and n >= 3 (row indices).
+__device__ __forceinline__ int fold_near(int i, int n) {
+  if (i < 0) i = -i;
+  if (i >= n) i = 2 * (n - 1) - i;
+  if (i < 0) i = -i;
+  return i;
+}
+
+__device__ __forceinline__ int mad24(int a, int b, int c) { return (int)__umul24((unsigned)a, (unsigned)b) + c; }
 
 // ------------------------------------------------------------- storage
 
 template <int PREC> struct Store;
 template <> struct Store<IGSP_FP32> {
   using T = float;
-  __device__ static float round(float v) { return v; }
+  static constexpr bool kSquare = true;
   __device__ static float widen(float v) { return v; }
 };
 template <> struct Store<IGSP_FP16> {
   using T = uint16_t;
-  __device__ static float round(float v) { return __half2float(__float2half_rn(v)); }
+  static constexpr bool kSquare = false;
   __device__ static uint16_t pack(float v) { return __half_as_ushort(__float2half_rn(v)); }
+  __device__ static uint32_t pack2(float a, float b) { return (uint32_t)pack(a) | ((uint32_t)pack(b) << 16); }
   __device__ static float widen(uint16_t b) { return __half2float(__ushort_as_half(b)); }
 };
 template <> struct Store<IGSP_BF16> {
   using T = uint16_t;
-  // round to nearest even on the top 16 bits (finite, non-negative inputs)
-  __device__ static uint16_t pack(float v) {
-    const uint32_t u = __float_as_uint(v);
-    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  static constexpr bool kSquare = true;
+  // round to nearest even, two values per instruction (v_cvt_pk_bf16_f32)
+  __device__ static uint32_t pack2(float a, float b) {
+    const bf16x2 v = __builtin_convertvector(f32x2{a, b}, bf16x2);
+    uint32_t r;
+    __builtin_memcpy(&r, &v, 4);
+    return r;
   }
-  __device__ static float round(float v) { return __uint_as_float((uint32_t)pack(v) << 16); }
   __device__ static float widen(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 };
 
-__device__ __forceinline__ int hist_bin(float stored) {
-  int b = (int)(__float_as_uint(stored) >> 16) - (int)kKeyLo;
-  return b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
-}
+template <int PREC> struct Keys {
+  static constexpr uint32_t lo = Store<PREC>::kSquare ? kKeyLoSquare : kKeyLoRoot;
+  static constexpr int bins = Store<PREC>::kSquare ? kBinsSquare : kBinsRoot;
+};
 
 // Launch order of work-groups is round-robin over the 8 XCDs; map
 // consecutive blocks of one XCD onto consecutive items so that vertically
@@ -101,34 +139,42 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return x * q + (x < r ? x : r) + j;
 }
 
-// ------------------------------------------------------------- row staging
+// ------------------------------------------------------------- row input
 
-struct RowFetch {
-  uint4 v;     // this lane's 16-byte chunk
-  int delta;   // offset of the span start inside the first chunk
+typedef unsigned u32x3 __attribute__((ext_vector_type(3)));
+
+// Raw buffer descriptor over [base, base + bytes): the base lives in SGPRs,
+// lanes pass 32-bit offsets, and the hardware drops accesses past `bytes`.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+
+// The 12 bytes (4 RGB pixels) of one lane, straight from HBM. Rows have pitch
+// 3*W, so the offset is only byte aligned; gfx950 under the HSA ABI runs
+// buffer loads in unaligned mode, and a wave's 64 lanes read 768 contiguous
+// bytes. Every lane issues exactly one load per row (so the wait for a row
+// never has to drain the prefetch of the next one): a lane whose columns
+// cross a view border loads the 4-pixel window that holds their mirror
+// images and puts them in order after the gray conversion.
+struct Lane12 {
+  u32x3 v;
 };
 
-__device__ __forceinline__ RowFetch fetch_row(const uint8_t* images, int64_t img_end, const uint8_t* span,
-                                              int span_bytes, int lane) {
-  RowFetch f;
-  const uintptr_t s = reinterpret_cast<uintptr_t>(span);
-  const uintptr_t a = s & ~uintptr_t(15);
-  f.delta = (int)(s - a);
-  const int nchunk = (span_bytes + f.delta + 15) >> 4;
-  f.v = make_uint4(0, 0, 0, 0);
-  if (lane < nchunk) {
-    const uint8_t* src = reinterpret_cast<const uint8_t*>(a) + 16 * lane;
-    const int64_t rel = (int64_t)(src - images);
-    if (rel + 16 <= img_end) {
-      f.v = *reinterpret_cast<const uint4*>(src);
-    } else {  // last chunk of the buffer: never read past the caller's bytes
-      uint32_t w[4] = {0, 0, 0, 0};
-      for (int k = 0; k < 16; ++k)
-        if (rel + k < img_end) w[k >> 2] |= (uint32_t)src[k] << (8 * (k & 3));
-      f.v = make_uint4(w[0], w[1], w[2], w[3]);
+__device__ __forceinline__ Lane12 load_lane(__amdgpu_buffer_rsrc_t row, int off) {
+  return Lane12{__builtin_amdgcn_raw_buffer_load_b96(row, off, 0, 0)};
+}
+
+// Views narrower than 4 pixels have no 4-pixel window: gather byte by byte.
+__device__ __forceinline__ Lane12 load_lane_bytes(__amdgpu_buffer_rsrc_t row, const int soff[4]) {
+  uint32_t w[3] = {0u, 0u, 0u};
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int k = 3 * i + c;
+      w[k >> 2] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(row, soff[i] + c, 0, 0) << (8 * (k & 3));
     }
-  }
-  return f;
+  return Lane12{u32x3{w[0], w[1], w[2]}};
 }
 
 // BT.601 luma x 1000 of 4 packed pixels (12 bytes in d0..d2) with byte dot
@@ -150,194 +196,266 @@ __device__ __forceinline__ void gray4(uint32_t d0, uint32_t d1, uint32_t d2, int
 
 // ------------------------------------------------------------- stage 1
 
-template <int PREC>
-__device__ __forceinline__ void wave_strip(const EdgeLaunch& L, const ViewDesc& vd, int x0, int ys, int ye,
-                                           uint8_t* stage, uint32_t* hist) {
-  using S = Store<PREC>;
-  const int lane = threadIdx.x & 63;
-  const int W = vd.W, H = vd.H;
-  const int cx0 = x0 - kHalo + kLanePx * lane;            // first input column of the lane
-  const bool interior = (x0 - kHalo >= 0) && (x0 - kHalo + kWaveCols <= W);
-  const int clo = max(0, x0 - kHalo), chi = min(W, x0 - kHalo + kWaveCols);
-  const int span_bytes = 3 * (chi - clo);
-  const uint8_t* img = L.images + vd.in_off;
-  const bool out_lane = lane >= 1 && lane <= 62;
-  const bool row_aligned = (W & 3) == 0;
+// Loop-carried state of one wavefront's march down its strip. Depth-one
+// windows are kept twice and addressed by the parity of the row, so after
+// unrolling the loop by two every value stays in its register (no copies).
+struct StripState {
+  Lane12 rows[2];                  // raw bytes: this row / next row
+  int h[2][4], s1[2][4], s2[2][4], s3[2][4];   // vertical (1 1)^4 cascade
+  int sx[2][4], u1[2][4];          // gx cascade
+  int bprev[2][4], d[2][4];        // gy: d(r) = b(r) - b(r-1), sy = d(r) + d(r-1)
+  float M[2][4];                   // squared magnitude, last two rows
+  float Mpp[4];                    // and the row before
+  float fx[2][4], fy[2][4];        // gradient of the last two rows (exact in float for |g| < 2^24,
+                                   // else rounded; only its orientation is read back)
+};
 
-  int soff[4];  // byte offsets of this lane's pixels inside the staged span
+struct StripCtx {
+  const uint8_t* img;
+  int64_t pitch;                   // 3 * W
+  int W, H, ys, ye, T;
+  bool remap;                      // some lane reorders its window (wave-uniform)
+  int win_off;                     // byte offset of the lane's 4-pixel window
+  bool sel0[4], sel1[4];           // pixel i of the lane = window pixel (sel1 sel0)
+  int soff[4];                     // byte offsets of the lane's mirrored columns
+  int store_off[4];                // byte offset of output pixel i in its map row, or
+                                   // past the row's end (dropped) if not an output
+  bool out_px[4];                  // pixel i is an output of this strip
+  uint8_t* map;                    // this view's map
+};
+
+// Offset past any map row: buffer accesses beyond a descriptor's size are
+// dropped by the hardware, so every lane can issue the same stores.
+constexpr int kDropOffset = 0x40000000;
+
+template <bool NARROW>
+__device__ __forceinline__ Lane12 fetch_row(const StripCtx& C, int yy) {
+  const __amdgpu_buffer_rsrc_t row = buffer_rsrc(C.img + fold_near(yy, C.H) * C.pitch, 3 * C.W);
+  if constexpr (NARROW) return load_lane_bytes(row, C.soff);
+  else return load_lane(row, C.win_off);
+}
+
+template <int PREC, bool NARROW, bool ALIGNED, int P>
+__device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int t, uint32_t* hist) {
+  using St = Store<PREC>;
+  constexpr int Q = P ^ 1;  // previous row's slot
+  constexpr int ES = sizeof(typename St::T);
+  // ---- prefetch the next row (the last step re-reads a row: one load per
+  //      step keeps the wait for this row from draining the prefetch)
+  S.rows[Q] = fetch_row<NARROW>(C, min(C.ys - kHalo + t + 1, C.ye + kHalo - 1));
+
+  // ---- 1. grayscale of row yy = ys - 4 + t
+  int g[4];
+  gray4(S.rows[P].v.x, S.rows[P].v.y, S.rows[P].v.z, g);
+  if (!NARROW && C.remap) {  // edge strips: mirrored columns into lane order
+    const int w0 = g[0], w1 = g[1], w2 = g[2], w3 = g[3];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int sc = fold(cx0 + i, W);
-    sc = sc < clo ? clo : (sc >= chi ? chi - 1 : sc);
-    soff[i] = 3 * (sc - clo);
+    for (int i = 0; i < 4; ++i) g[i] = C.sel1[i] ? (C.sel0[i] ? w3 : w2) : (C.sel0[i] ? w1 : w0);
   }
 
-  int hp[4] = {}, s1p[4] = {}, s2p[4] = {}, s3p[4] = {};
-  int bp[4] = {}, bpp[4] = {};
-  int sxp[4] = {}, u1p[4] = {};
-  float Mp[4] = {}, Mpp[4] = {};
-  int codep[4] = {};
+  // ---- 2. horizontal binomial taps (1 4 6 4 1)
+  const int gL2 = from_left(g[2]), gL3 = from_left(g[3]);
+  const int gR0 = from_right(g[0]), gR1 = from_right(g[1]);
+  int h[4];
+  h[0] = mad24(g[0], 6, (gL2 + g[2]) + 4 * (gL3 + g[1]));
+  h[1] = mad24(g[1], 6, (gL3 + g[3]) + 4 * (g[0] + g[2]));
+  h[2] = mad24(g[2], 6, (g[0] + gR0) + 4 * (g[1] + g[3]));
+  h[3] = mad24(g[3], 6, (g[1] + gR1) + 4 * (g[2] + gR0));
 
+  // ---- 3. vertical taps as four (1 1) sums: b = blur of row yy-2
+  int b[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    S.h[P][i] = h[i];
+    S.s1[P][i] = h[i] + S.h[Q][i];
+    S.s2[P][i] = S.s1[P][i] + S.s1[Q][i];
+    S.s3[P][i] = S.s2[P][i] + S.s2[Q][i];
+    b[i] = S.s3[P][i] + S.s3[Q][i];
+  }
+
+  // ---- 4. Sobel of row yy-3: gx = (1 2 1)^T on the horizontal difference,
+  //      gy = (1 2 1) along x on the vertical difference b(r+1) - b(r-1)
+  const int bL = from_left(b[3]), bR = from_right(b[0]);
+  S.sx[P][0] = b[1] - bL;
+  S.sx[P][1] = b[2] - b[0];
+  S.sx[P][2] = b[3] - b[1];
+  S.sx[P][3] = bR - b[2];
+  int gx[4], sy[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    S.u1[P][i] = S.sx[P][i] + S.sx[Q][i];
+    gx[i] = S.u1[P][i] + S.u1[Q][i];
+    S.d[P][i] = b[i] - S.bprev[Q][i];
+    S.bprev[P][i] = b[i];
+    sy[i] = S.d[P][i] + S.d[Q][i];
+  }
+  const int syL = from_left(sy[3]), syR = from_right(sy[0]);
+  const int gy[4] = {syL + 2 * sy[0] + sy[1], sy[0] + 2 * sy[1] + sy[2], sy[1] + 2 * sy[2] + sy[3],
+                     sy[2] + 2 * sy[3] + syR};
+
+  // ---- 5. squared magnitude of row yy-3
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    S.fx[P][i] = (float)gx[i];
+    S.fy[P][i] = (float)gy[i];
+    S.M[P][i] = __builtin_fmaf(S.fx[P][i], S.fx[P][i], S.fy[P][i] * S.fy[P][i]);
+  }
+
+  // ---- 6. suppression of row c = yy-4: up = Mpp, centre = M[Q], down = M[P]
+  // (rows before the strip's first output are computed too and their stores
+  // dropped, so the loop body has no branch around memory operations)
   const float kTan = 0.41421356237309503f;  // tan(22.5 deg) = sqrt(2) - 1
-  const int T = (ye - ys) + 2 * kHalo;
-
-  RowFetch nxt = fetch_row(L.images, L.img_end, img + (int64_t)fold(ys - kHalo, H) * 3 * W + 3 * clo,
-                           span_bytes, lane);
-  for (int t = 0; t < T; ++t) {
-    // ---- stage this row's bytes, prefetch the next row
-    *reinterpret_cast<uint4*>(stage + 16 * lane) = nxt.v;
-    const int delta = nxt.delta;
-    if (t + 1 < T)
-      nxt = fetch_row(L.images, L.img_end, img + (int64_t)fold(ys - kHalo + t + 1, H) * 3 * W + 3 * clo,
-                      span_bytes, lane);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    // ---- 1. grayscale
-    int g[4];
-    if (interior) {
-      const int off = 12 * lane + delta;
-      const uint32_t* s32 = reinterpret_cast<const uint32_t*>(stage + (off & ~3));
-      const uint32_t w0 = s32[0], w1 = s32[1], w2 = s32[2], w3 = s32[3];
-      const int sh = off & 3;
-      gray4(__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh),
-            __builtin_amdgcn_alignbyte(w3, w2, sh), g);
+  const int c = C.ys - 2 * kHalo + t;
+  const bool row_out = t >= 2 * kHalo;
+  const float* Mu = S.Mpp;
+  const float* Mc = S.M[Q];
+  const float* Md = S.M[P];
+  const float uL = from_left(Mu[3]), uR = from_right(Mu[0]);
+  const float cL = from_left(Mc[3]), cR = from_right(Mc[0]);
+  const float dL = from_left(Md[3]), dR = from_right(Md[0]);
+  float q[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float Ul = i > 0 ? Mu[i - 1] : uL, Uc = Mu[i], Ur = i < 3 ? Mu[i + 1] : uR;
+    const float Cl = i > 0 ? Mc[i - 1] : cL, Cr = i < 3 ? Mc[i + 1] : cR;
+    const float Dl = i > 0 ? Md[i - 1] : dL, Dc = Md[i], Dr = i < 3 ? Md[i + 1] : dR;
+    // orientation bin: within 22.5 degrees of the x axis, of the y axis, or
+    // diagonal (gx, gy of equal sign: (1,1), else (1,-1)); tan 22.5 = sqrt 2 - 1
+    const float fx = S.fx[Q][i], fy = S.fy[Q][i];
+    const float ax = __builtin_fabsf(fx), ay = __builtin_fabsf(fy);
+    const bool cH = ay < kTan * ax;
+    const bool cV = ax < kTan * ay;
+    const bool c45 = (__float_as_int(fx) ^ __float_as_int(fy)) >= 0;
+    // A = p - e, B = p + e for the axis e of the bin: x, y, (1,1), (1,-1)
+    const float A = cH ? Cl : (cV ? Uc : (c45 ? Ul : Dl));
+    const float B = cH ? Cr : (cV ? Dc : (c45 ? Dr : Ur));
+    const float m = Mc[i];
+    // keep iff M(p) > M(p - d) and M(p) >= M(p + d), d = +e or -e
+    // (bitwise, so the decision stays in lane masks instead of branches)
+    const bool neg = (cV ? fy : fx) < 0.0f;
+    const bool keep = ((neg & (m > B) & (m >= A)) | (!neg & (m > A) & (m >= B))) & (m > 0.0f);
+    const float v = St::kSquare ? m : __builtin_amdgcn_sqrtf(m) * kStoreScaleRoot;
+    q[i] = keep ? v : 0.0f;
+  }
+  const __amdgpu_buffer_rsrc_t mrow =
+      buffer_rsrc(C.map + (int64_t)max(c, 0) * C.W * ES, row_out ? C.W * ES : 0);
+  uint32_t bits[4];  // stored value widened to float32, for the histogram
+  if constexpr (PREC == IGSP_FP32) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bits[i] = __float_as_uint(q[i]);
+    if constexpr (ALIGNED) {
+      __builtin_amdgcn_raw_buffer_store_b128(u32x4{bits[0], bits[1], bits[2], bits[3]}, mrow, C.store_off[0], 0, 0);
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint8_t* p = stage + soff[i] + delta;
-        g[i] = 299 * (int)p[0] + 587 * (int)p[1] + 114 * (int)p[2];
-      }
+      for (int i = 0; i < 4; ++i) __builtin_amdgcn_raw_buffer_store_b32(bits[i], mrow, C.store_off[i], 0, 0);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+  } else {
+    const uint32_t w0 = St::pack2(q[0], q[1]), w1 = St::pack2(q[2], q[3]);
+    bits[0] = w0 << 16;
+    bits[1] = w0 & 0xFFFF0000u;
+    bits[2] = w1 << 16;
+    bits[3] = w1 & 0xFFFF0000u;
+    if constexpr (ALIGNED) {
+      __builtin_amdgcn_raw_buffer_store_b64(u32x2{w0, w1}, mrow, C.store_off[0], 0, 0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(bits[i] >> 16), mrow, C.store_off[i], 0, 0);
+    }
+    if constexpr (PREC == IGSP_FP16) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bits[i] = __float_as_uint(St::widen((uint16_t)(bits[i] >> 16)));
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (row_out && bits[i] != 0u && C.out_px[i])
+      atomicAdd(&hist[min(max((int)(bits[i] >> 16) - (int)Keys<PREC>::lo, 0), Keys<PREC>::bins - 1)], 1u);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) S.Mpp[i] = S.M[Q][i];
+}
 
-    // ---- 2. horizontal binomial taps (1 4 6 4 1)
-    const int gL2 = from_left(g[2]), gL3 = from_left(g[3]);
-    const int gR0 = from_right(g[0]), gR1 = from_right(g[1]);
-    int h[4];
-    h[0] = (gL2 + g[2]) + 4 * (gL3 + g[1]) + 6 * g[0];
-    h[1] = (gL3 + g[3]) + 4 * (g[0] + g[2]) + 6 * g[1];
-    h[2] = (g[0] + gR0) + 4 * (g[1] + g[3]) + 6 * g[2];
-    h[3] = (g[1] + gR1) + 4 * (g[2] + gR0) + 6 * g[3];
-
-    // ---- 3. vertical taps as four (1 1) sums: b = blur of row yy-2
-    int b[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int s1 = h[i] + hp[i], s2 = s1 + s1p[i], s3 = s2 + s2p[i];
-      b[i] = s3 + s3p[i];
-      hp[i] = h[i]; s1p[i] = s1; s2p[i] = s2; s3p[i] = s3;
-    }
-
-    // ---- 4. Sobel: gx(yy-3) = (1 2 1)^T on the horizontal difference
-    const int bL = from_left(b[3]), bR = from_right(b[0]);
-    int sx[4] = {b[1] - bL, b[2] - b[0], b[3] - b[1], bR - b[2]};
-    int gx[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int u1 = sx[i] + sxp[i];
-      gx[i] = u1 + u1p[i];
-      sxp[i] = sx[i]; u1p[i] = u1;
-    }
-    //      gy(yy-3) = (1 2 1) along x on the vertical difference
-    int sy[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      sy[i] = b[i] - bpp[i];
-      bpp[i] = bp[i]; bp[i] = b[i];
-    }
-    const int syL = from_left(sy[3]), syR = from_right(sy[0]);
-    int gy[4] = {syL + 2 * sy[0] + sy[1], sy[0] + 2 * sy[1] + sy[2], sy[1] + 2 * sy[2] + sy[3],
-                 sy[2] + 2 * sy[3] + syR};
-
-    // ---- 5. magnitude and orientation of row yy-3
-    float M[4];
-    int code[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float fx = (float)gx[i], fy = (float)gy[i];
-      M[i] = __builtin_fmaf(fx, fx, fy * fy);
-      const float ax = __builtin_fabsf(fx), ay = __builtin_fabsf(fy);
-      const bool isH = ay < kTan * ax;
-      const bool isV = ax < kTan * ay;
-      const int sel = isH ? 0 : (isV ? 1 : (((gx[i] ^ gy[i]) >= 0) ? 2 : 3));
-      const bool neg = isV ? (gy[i] < 0) : (gx[i] < 0);
-      code[i] = sel | (neg ? 4 : 0);
-    }
-
-    // ---- 6. suppression of row yy-4 (up = Mpp, centre = Mp, down = M)
-    if (t >= 2 * kHalo) {
-      const int c = ys - 2 * kHalo + t;
-      const float uL = from_left(Mpp[3]), uR = from_right(Mpp[0]);
-      const float cL = from_left(Mp[3]), cR = from_right(Mp[0]);
-      const float dL = from_left(M[3]), dR = from_right(M[0]);
-      float val[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float Ul = i > 0 ? Mpp[i - 1] : uL, Uc = Mpp[i], Ur = i < 3 ? Mpp[i + 1] : uR;
-        const float Cl = i > 0 ? Mp[i - 1] : cL, Cr = i < 3 ? Mp[i + 1] : cR;
-        const float Dl = i > 0 ? M[i - 1] : dL, Dc = M[i], Dr = i < 3 ? M[i + 1] : dR;
-        const int sel = codep[i] & 3;
-        // A = p - e, B = p + e for the axis e of the bin: x, y, (1,1), (1,-1)
-        const float A = sel == 0 ? Cl : (sel == 1 ? Uc : (sel == 2 ? Ul : Dl));
-        const float B = sel == 0 ? Cr : (sel == 1 ? Dc : (sel == 2 ? Dr : Ur));
-        const bool neg = (codep[i] & 4) != 0;
-        const float lo = neg ? B : A, hi = neg ? A : B;   // M(p - d), M(p + d)
-        const float m = Mp[i];
-        const bool keep = (m > lo) && (m >= hi) && (m > 0.0f);
-        val[i] = keep ? S::round(__builtin_amdgcn_sqrtf(m) * kStoreScale) : 0.0f;
-      }
-      if (out_lane && cx0 < W) {
-        typename S::T* mrow = reinterpret_cast<typename S::T*>(L.map) + vd.map_off + (int64_t)c * W + cx0;
-        if (row_aligned) {
-          if constexpr (PREC == IGSP_FP32) {
-            *reinterpret_cast<float4*>(mrow) = make_float4(val[0], val[1], val[2], val[3]);
-          } else {
-            const uint32_t lo2 = (uint32_t)S::pack(val[0]) | ((uint32_t)S::pack(val[1]) << 16);
-            const uint32_t hi2 = (uint32_t)S::pack(val[2]) | ((uint32_t)S::pack(val[3]) << 16);
-            *reinterpret_cast<uint2*>(mrow) = make_uint2(lo2, hi2);
-          }
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (cx0 + i < W) {
-              if constexpr (PREC == IGSP_FP32) mrow[i] = val[i];
-              else mrow[i] = S::pack(val[i]);
-            }
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (val[i] > 0.0f && cx0 + i < W) atomicAdd(&hist[hist_bin(val[i])], 1u);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      Mpp[i] = Mp[i]; Mp[i] = M[i]; codep[i] = code[i];
-    }
+template <int PREC, bool NARROW, bool ALIGNED>
+__device__ __forceinline__ void march(const StripCtx& C, uint32_t* hist) {
+  StripState S = {};
+  S.rows[0] = fetch_row<NARROW>(C, C.ys - kHalo);
+  for (int t = 0; t < C.T; t += 2) {
+    strip_row<PREC, NARROW, ALIGNED, 0>(C, S, t, hist);
+    if (t + 1 < C.T) strip_row<PREC, NARROW, ALIGNED, 1>(C, S, t + 1, hist);
   }
 }
 
+template <int PREC>
+__device__ __forceinline__ void wave_strip(const EdgeLaunch& L, const ViewDesc& vd, int x0, int ys, int ye,
+                                           uint32_t* hist) {
+  using St = Store<PREC>;
+  constexpr int ES = sizeof(typename St::T);
+  const int lane = __lane_id();
+  StripCtx C;
+  C.W = vd.W;
+  C.H = vd.H;
+  C.ys = ys;
+  C.ye = ye;
+  C.T = (ye - ys) + 2 * kHalo;
+  C.img = L.images + vd.in_off;
+  C.pitch = 3 * (int64_t)vd.W;
+  C.map = reinterpret_cast<uint8_t*>(reinterpret_cast<typename St::T*>(L.map) + vd.map_off);
+  const int cx0 = x0 - kHalo + kLanePx * lane;            // first input column of the lane
+  int sc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    sc[i] = fold(cx0 + i, C.W);
+    C.soff[i] = 3 * sc[i];
+  }
+  // 4-pixel window holding the lane's (possibly mirrored) columns: its own
+  // columns inside the view, else the smallest in-bounds window that covers
+  // the mirror images (lanes wholly past the border only feed halo columns)
+  int ws = cx0;
+  if (cx0 < 0 || cx0 + 3 >= C.W) {
+    ws = min(min(sc[0], sc[1]), min(sc[2], sc[3]));
+    ws = min(ws, C.W - 4);
+  }
+  ws = max(ws, 0);
+  C.win_off = 3 * ws;
+  bool ident = true;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int k = min(max(sc[i] - ws, 0), 3);
+    C.sel0[i] = (k & 1) != 0;
+    C.sel1[i] = (k & 2) != 0;
+    ident = ident && k == i;
+  }
+  const bool narrow = C.W < 4;
+  C.remap = !narrow && __builtin_amdgcn_ballot_w64(!ident) != 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    C.out_px[i] = lane >= 1 && lane <= 62 && cx0 + i < C.W;
+    C.store_off[i] = C.out_px[i] ? (cx0 + i) * ES : kDropOffset;
+  }
+  const bool aligned = (C.W & 3) == 0;  // then a lane's 4 outputs are all in or all out
+  if (narrow) march<PREC, true, false>(C, hist);
+  else if (aligned) march<PREC, false, true>(C, hist);
+  else march<PREC, false, false>(C, hist);
+}
+
 template <int PREC, int NW>
-__global__ __launch_bounds__(NW * 64) void edge_fused_kernel(EdgeLaunch L, int item0, int n_items) {
-  __shared__ uint32_t hist[kBins];
-  __shared__ __align__(16) uint8_t stage[NW][kStageBytes];
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(IGSP_FUSED_WAVES_PER_EU))) void edge_fused_kernel(EdgeLaunch L, int item0, int n_items) {
+  constexpr int NB = Keys<PREC>::bins;
+  __shared__ uint32_t hist[NB];
   const int item = item0 + xcd_remap((int)blockIdx.x, n_items);
   const EdgeItem it = L.items[item];
   const ViewDesc vd = L.views[it.view];
-  for (int i = threadIdx.x; i < kBins; i += NW * 64) hist[i] = 0;
+  for (int i = threadIdx.x; i < NB; i += NW * 64) hist[i] = 0;
   __syncthreads();
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ys = it.y0 + w * L.seg_rows;
   const int ye = min(ys + L.seg_rows, it.y0 + it.rows);
-  if (ys < ye) wave_strip<PREC>(L, vd, it.x0, ys, ye, stage[w], hist);
+  if (ys < ye) wave_strip<PREC>(L, vd, it.x0, ys, ye, hist);
   __syncthreads();
-  uint32_t* gh = L.hist + (int64_t)it.view * kBins;
-  for (int i = threadIdx.x; i < kBins; i += NW * 64) {
+  gptr<uint32_t> gh = as_global(L.hist) + (int64_t)it.view * kBinsMax;
+  for (int i = threadIdx.x; i < NB; i += NW * 64) {
     const uint32_t c = hist[i];
-    if (c) atomicAdd(&gh[i], c);
+    if (c) atomicAdd((uint32_t*)(gh + i), c);
   }
 }
 
@@ -350,7 +468,11 @@ __device__ __forceinline__ int final_shift(int prec) {
 
 __device__ __forceinline__ void finish_view(const EdgeLaunch& L, int v, MedState& st) {
   st.med = st.n ? __uint_as_float(st.prefix << st.shift) : 0.0f;
-  if (L.medians_dn) L.medians_dn[v] = st.med * (8192.0f / 256000.0f);
+  if (L.medians_dn) {
+    // back to DN per pixel of an unnormalised Sobel: sqrt(M) / 256000
+    const float m = L.precision == IGSP_FP16 ? st.med * 8192.0f : sqrtf(st.med);
+    L.medians_dn[v] = m * (1.0f / 256000.0f);
+  }
   if (L.survivors) L.survivors[v] = (int32_t)st.n;
 }
 
@@ -372,12 +494,14 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, u
   return before + x - v;
 }
 
+template <int PREC>
 __global__ __launch_bounds__(256) void median_select_kernel(EdgeLaunch L, int v0) {
+  constexpr int NB = Keys<PREC>::bins;
+  constexpr int PER = NB / 256;
+  static_assert(NB % 256 == 0, "bins per thread");
   __shared__ uint32_t tmp[4];
   const int v = v0 + blockIdx.x;
-  uint32_t* h = L.hist + (int64_t)v * kBins;
-  constexpr int PER = kBins / 256;
-  static_assert(kBins % 256 == 0, "bins per thread");
+  uint32_t* h = L.hist + (int64_t)v * kBinsMax;
   const int b0 = threadIdx.x * PER;
   uint32_t c[PER];
   uint32_t sum = 0;
@@ -400,8 +524,8 @@ __global__ __launch_bounds__(256) void median_select_kernel(EdgeLaunch L, int v0
       if (cum + c[j] > k) { b = b0 + j; break; }
       cum += c[j];
     }
-    MedState st = {kKeyLo + (uint32_t)b, 16, k - cum, n, 0.0f, {0u, 0u, 0u}};
-    if (16 == final_shift(L.precision)) finish_view(L, v, st);
+    MedState st = {Keys<PREC>::lo + (uint32_t)b, 16, k - cum, n, 0.0f, {0u, 0u, 0u}};
+    if (16 == final_shift(PREC)) finish_view(L, v, st);
     L.state[v] = st;
   }
 #pragma unroll
@@ -409,8 +533,25 @@ __global__ __launch_bounds__(256) void median_select_kernel(EdgeLaunch L, int v0
 }
 
 template <int PREC>
-__global__ __launch_bounds__(256) void median_refine_kernel(EdgeLaunch L, int flat0, int digit_bits) {
+__device__ __forceinline__ void load8(const typename Store<PREC>::T* m, int64_t p, float v[8]) {
   using S = Store<PREC>;
+  if constexpr (PREC == IGSP_FP32) {
+    const f32x4 a = *as_global(reinterpret_cast<const f32x4*>(m + p));
+    const f32x4 b = *as_global(reinterpret_cast<const f32x4*>(m + p + 4));
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    const u32x4 q = *as_global(reinterpret_cast<const u32x4*>(m + p));
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[2 * k] = S::widen((uint16_t)(w[k] & 0xFFFF));
+      v[2 * k + 1] = S::widen((uint16_t)(w[k] >> 16));
+    }
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void median_refine_kernel(EdgeLaunch L, int flat0, int digit_bits) {
   __shared__ uint32_t hs[kRefineBins];
   const FlatItem it = L.flat[flat0 + blockIdx.x];
   const MedState st = L.state[it.view];
@@ -420,19 +561,12 @@ __global__ __launch_bounds__(256) void median_refine_kernel(EdgeLaunch L, int fl
   if (st.n > 0 && st.shift > final_shift(PREC)) {
     const int dshift = st.shift - digit_bits;
     const uint32_t dmask = (1u << digit_bits) - 1u;
-    const typename S::T* m = reinterpret_cast<const typename S::T*>(L.map) + vd.map_off;
-    for (int64_t p = it.p0 + 4 * threadIdx.x; p < it.p1; p += 4 * 256) {
-      float v[4];
-      if constexpr (PREC == IGSP_FP32) {
-        const float4 q = *reinterpret_cast<const float4*>(m + p);
-        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-      } else {
-        const uint2 q = *reinterpret_cast<const uint2*>(m + p);
-        v[0] = S::widen((uint16_t)(q.x & 0xFFFF)); v[1] = S::widen((uint16_t)(q.x >> 16));
-        v[2] = S::widen((uint16_t)(q.y & 0xFFFF)); v[3] = S::widen((uint16_t)(q.y >> 16));
-      }
+    const typename Store<PREC>::T* m = reinterpret_cast<const typename Store<PREC>::T*>(L.map) + vd.map_off;
+    for (int64_t p = it.p0 + 8 * threadIdx.x; p < it.p1; p += 8 * 256) {
+      float v[8];
+      load8<PREC>(m, p, v);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < 8; ++i) {
         const uint32_t bits = __float_as_uint(v[i]);
         if (p + i < it.p1 && v[i] > 0.0f && (bits >> st.shift) == st.prefix)
           atomicAdd(&hs[(bits >> dshift) & dmask], 1u);
@@ -466,35 +600,391 @@ __global__ __launch_bounds__(256) void refine_select_kernel(EdgeLaunch L, int v0
 // ------------------------------------------------------------- stage 3
 
 template <int PREC>
+__device__ __forceinline__ void normalise8(const float v[8], float med, float inv, float e[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    // the stored median itself maps to exactly 1
+    const float r = v[i] == med ? 1.0f : v[i] * inv;
+    e[i] = v[i] > 0.0f ? (Store<PREC>::kSquare ? __builtin_amdgcn_sqrtf(r) : r) : 0.0f;
+  }
+}
+
+// Element-wise normalisation of one flat chunk of a view. Each thread keeps
+// kNormUnroll groups of 8 stored values in flight before converting and
+// storing them, so a wave has several 1 KB loads outstanding.
+constexpr int kNormUnroll = 2;
+
+template <int PREC>
 __global__ __launch_bounds__(256) void normalise_kernel(EdgeLaunch L, int flat0) {
-  using S = Store<PREC>;
   const FlatItem it = L.flat[flat0 + blockIdx.x];
   const ViewDesc vd = L.views[it.view];
   const float med = L.state[it.view].med;
-  const typename S::T* m = reinterpret_cast<const typename S::T*>(L.map) + vd.map_off;
-  float* out = L.out + vd.out_off;
+  const float inv = med > 0.0f ? 1.0f / med : 0.0f;
+  const typename Store<PREC>::T* m = reinterpret_cast<const typename Store<PREC>::T*>(L.map) + vd.map_off;
+  gptr<float> out = as_global(L.out + vd.out_off);
   const bool aligned = (vd.out_off & 3) == 0;
-  for (int64_t p = it.p0 + 4 * threadIdx.x; p < it.p1; p += 4 * 256) {
-    float v[4];
-    if constexpr (PREC == IGSP_FP32) {
-      const float4 q = *reinterpret_cast<const float4*>(m + p);
-      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    } else {
-      const uint2 q = *reinterpret_cast<const uint2*>(m + p);
-      v[0] = S::widen((uint16_t)(q.x & 0xFFFF)); v[1] = S::widen((uint16_t)(q.x >> 16));
-      v[2] = S::widen((uint16_t)(q.y & 0xFFFF)); v[3] = S::widen((uint16_t)(q.y >> 16));
-    }
-    float e[4];
+  constexpr int STEP = 8 * 256;
+  for (int64_t p0 = it.p0 + 8 * threadIdx.x; p0 < it.p1; p0 += kNormUnroll * STEP) {
+    float v[kNormUnroll][8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) e[i] = v[i] > 0.0f ? v[i] / med : 0.0f;
-    if (aligned && p + 4 <= it.p1) {
-      *reinterpret_cast<float4*>(out + p) = make_float4(e[0], e[1], e[2], e[3]);
-    } else {
+    for (int u = 0; u < kNormUnroll; ++u)
+      if (p0 + u * STEP < it.p1) load8<PREC>(m, p0 + u * STEP, v[u]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (p + i < it.p1) out[p + i] = e[i];
+    for (int u = 0; u < kNormUnroll; ++u) {
+      const int64_t p = p0 + u * STEP;
+      if (p >= it.p1) break;
+      float e[8];
+      normalise8<PREC>(v[u], med, inv, e);
+      if (aligned && p + 8 <= it.p1) {
+        *(gptr<f32x4>)(out + p) = f32x4{e[0], e[1], e[2], e[3]};
+        *(gptr<f32x4>)(out + p + 4) = f32x4{e[4], e[5], e[6], e[7]};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (p + i < it.p1) out[p + i] = e[i];
+      }
     }
   }
+}
+
+// ------------------------------------------------------------- persistent form
+//
+// The batched pipeline as one launch: resident work-groups take tasks from a
+// queue in list order. A view's stencil items come first; each later phase
+// (refinement passes, normalisation) of the view sits a window of other
+// views' work behind it, so memory-bound normalisation of earlier views runs
+// beside the ALU-bound stencil of later ones. The work-group that finishes a
+// phase's last task runs that view's selection step and publishes it; tasks
+// of the next phase wait for it. Every task waited on was handed out
+// earlier, to a work-group that is already running, so the waits end.
+
+// Bound of one wait (about half a second of polling); never reached when the
+// waited-on work is running. If it were, the launch records an error bit and
+// finishes instead of hanging.
+constexpr uint32_t kSpinLimit = 1u << 19;
+
+__device__ __forceinline__ uint32_t ld_agent(uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// MedState through device-coherent accesses (it is written by other
+// work-groups of the same launch).
+__device__ __forceinline__ MedState load_state(MedState* s) {
+  uint32_t* p = reinterpret_cast<uint32_t*>(s);
+  MedState r;
+  r.prefix = ld_agent(p);
+  r.shift = (int32_t)ld_agent(p + 1);
+  r.rank = ld_agent(p + 2);
+  r.n = ld_agent(p + 3);
+  r.med = __uint_as_float(ld_agent(p + 4));
+  r.pad[0] = r.pad[1] = r.pad[2] = 0u;
+  return r;
+}
+__device__ __forceinline__ void store_state(MedState* s, const MedState& r) {
+  uint32_t* p = reinterpret_cast<uint32_t*>(s);
+  st_agent(p, r.prefix);
+  st_agent(p + 1, (uint32_t)r.shift);
+  st_agent(p + 2, r.rank);
+  st_agent(p + 3, r.n);
+  st_agent(p + 4, __float_as_uint(r.med));
+}
+
+// Exclusive scan over a work-group of NW waves; `total` gets the sum.
+template <int NW>
+__device__ __forceinline__ uint32_t wg_excl_scan(uint32_t v, uint32_t* tmp, uint32_t& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) tmp[w] = x;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const uint32_t t = tmp[k];
+    if (k < w) before += t;
+    tot += t;
+  }
+  total = tot;
+  __syncthreads();
+  return before + x - v;
+}
+
+// The end of one task: make this work-group's writes visible device-wide,
+// count the task off its phase, and tell every thread whether it was the
+// phase's last (then the count is restored for the next launch and the
+// other tasks' writes are acquired).
+template <int NW>
+__device__ __forceinline__ bool arrive(uint32_t* left, uint32_t restore, uint32_t* s_flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t old = __hip_atomic_fetch_add(left, 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool last = old == 1u;
+    if (last) {
+      st_agent(left, restore);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    *s_flag = last ? 1u : 0u;
+  }
+  __syncthreads();
+  return *s_flag != 0u;
+}
+
+// Publish a view's selection step `level` (all threads call it).
+__device__ __forceinline__ void publish(uint32_t* ready, uint32_t level) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) st_agent(ready, level);
+}
+
+// Wait until a view's selection has reached `level` (all threads call it).
+__device__ __forceinline__ void await(uint32_t* ready, uint32_t level, uint32_t* error) {
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (ld_agent(ready) < level) {
+      __builtin_amdgcn_s_sleep(8);
+      if (++spins == kSpinLimit) {
+        atomicOr(error, 1u);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// First selection step of view v from its global histogram (then cleared).
+template <int PREC, int NW>
+__device__ void select_hist(const EdgeLaunch& L, int v, uint32_t* tmp) {
+  constexpr int NT = NW * 64, NB = Keys<PREC>::bins, PER = (NB + NT - 1) / NT;
+  uint32_t* h = L.hist + (int64_t)v * kBinsMax;
+  const int b0 = threadIdx.x * PER;
+  uint32_t sum = 0;
+  for (int k = 0; k < PER; ++k)
+    if (b0 + k < NB) sum += ld_agent(h + b0 + k);
+  uint32_t n = 0;
+  const uint32_t excl = wg_excl_scan<NW>(sum, tmp, n);
+  const uint32_t k = n ? (n - 1) / 2 : 0;
+  if (n == 0) {
+    if (threadIdx.x == 0) {
+      MedState st = {0u, 0, 0u, 0u, 0.0f, {0u, 0u, 0u}};
+      finish_view(L, v, st);
+      store_state(L.state + v, st);
+    }
+  } else if (excl <= k && k < excl + sum) {
+    uint32_t cum = excl;
+    int b = b0;
+    for (int j = 0; j < PER && b0 + j < NB; ++j) {
+      const uint32_t c = ld_agent(h + b0 + j);
+      if (cum + c > k) {
+        b = b0 + j;
+        break;
+      }
+      cum += c;
+    }
+    MedState st = {Keys<PREC>::lo + (uint32_t)b, 16, k - cum, n, 0.0f, {0u, 0u, 0u}};
+    if (16 == final_shift(PREC)) finish_view(L, v, st);
+    store_state(L.state + v, st);
+  }
+  for (int j = 0; j < PER; ++j)
+    if (b0 + j < NB) st_agent(h + b0 + j, 0u);
+}
+
+// A refinement selection step of view v from its digit histogram (then cleared).
+template <int NW>
+__device__ void select_refine(const EdgeLaunch& L, int v, int digit_bits, uint32_t* tmp) {
+  constexpr int NT = NW * 64, PER = (kRefineBins + NT - 1) / NT;
+  uint32_t* h = L.rhist + (int64_t)v * kRefineBins;
+  MedState st = load_state(L.state + v);
+  const int fin = final_shift(L.precision);
+  const int b0 = threadIdx.x * PER;
+  uint32_t sum = 0;
+  for (int j = 0; j < PER; ++j)
+    if (b0 + j < kRefineBins) sum += ld_agent(h + b0 + j);
+  uint32_t tot = 0;
+  const uint32_t excl = wg_excl_scan<NW>(sum, tmp, tot);
+  if (st.n > 0 && st.shift > fin && excl <= st.rank && st.rank < excl + sum) {
+    uint32_t cum = excl;
+    int b = b0;
+    for (int j = 0; j < PER && b0 + j < kRefineBins; ++j) {
+      const uint32_t c = ld_agent(h + b0 + j);
+      if (cum + c > st.rank) {
+        b = b0 + j;
+        break;
+      }
+      cum += c;
+    }
+    st.prefix = (st.prefix << digit_bits) | (uint32_t)b;
+    st.shift -= digit_bits;
+    st.rank -= cum;
+    if (st.shift == fin) finish_view(L, v, st);
+    store_state(L.state + v, st);
+  }
+  for (int j = 0; j < PER; ++j)
+    if (b0 + j < kRefineBins) st_agent(h + b0 + j, 0u);
+}
+
+// Digit histogram of one flat chunk for refinement pass `digit_bits`.
+template <int PREC, int NW>
+__device__ void refine_chunk(const EdgeLaunch& L, const FlatItem& it, const MedState& st, int digit_bits,
+                             uint32_t* hs) {
+  constexpr int NT = NW * 64;
+  for (int i = threadIdx.x; i < kRefineBins; i += NT) hs[i] = 0;
+  __syncthreads();
+  if (st.n > 0 && st.shift > final_shift(PREC)) {
+    const ViewDesc vd = L.views[it.view];
+    const int dshift = st.shift - digit_bits;
+    const uint32_t dmask = (1u << digit_bits) - 1u;
+    const typename Store<PREC>::T* m = reinterpret_cast<const typename Store<PREC>::T*>(L.map) + vd.map_off;
+    for (int64_t p = it.p0 + 8 * threadIdx.x; p < it.p1; p += 8 * NT) {
+      float v[8];
+      load8<PREC>(m, p, v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const uint32_t bits = __float_as_uint(v[i]);
+        if (p + i < it.p1 && v[i] > 0.0f && (bits >> st.shift) == st.prefix)
+          atomicAdd(&hs[(bits >> dshift) & dmask], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kRefineBins; i += NT) {
+    const uint32_t c = hs[i];
+    if (c) atomicAdd(&L.rhist[(int64_t)it.view * kRefineBins + i], c);
+  }
+}
+
+// Normalisation of one flat chunk.
+template <int PREC, int NW>
+__device__ void norm_chunk(const EdgeLaunch& L, const FlatItem& it, float med) {
+  constexpr int NT = NW * 64, STEP = 8 * NT;
+  const ViewDesc vd = L.views[it.view];
+  const float inv = med > 0.0f ? 1.0f / med : 0.0f;
+  const typename Store<PREC>::T* m = reinterpret_cast<const typename Store<PREC>::T*>(L.map) + vd.map_off;
+  gptr<float> out = as_global(L.out + vd.out_off);
+  const bool aligned = (vd.out_off & 3) == 0;
+  for (int64_t p0 = it.p0 + 8 * threadIdx.x; p0 < it.p1; p0 += kNormUnroll * STEP) {
+    float v[kNormUnroll][8];
+#pragma unroll
+    for (int u = 0; u < kNormUnroll; ++u)
+      if (p0 + u * STEP < it.p1) load8<PREC>(m, p0 + u * STEP, v[u]);
+#pragma unroll
+    for (int u = 0; u < kNormUnroll; ++u) {
+      const int64_t p = p0 + u * STEP;
+      if (p >= it.p1) break;
+      float e[8];
+      normalise8<PREC>(v[u], med, inv, e);
+      if (aligned && p + 8 <= it.p1) {
+        *(gptr<f32x4>)(out + p) = f32x4{e[0], e[1], e[2], e[3]};
+        *(gptr<f32x4>)(out + p + 4) = f32x4{e[4], e[5], e[6], e[7]};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (p + i < it.p1) out[p + i] = e[i];
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int refine_digit_bits(int prec) { return prec == IGSP_FP16 ? 3 : 8; }
+
+template <int PREC, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(IGSP_FUSED_WAVES_PER_EU))) void
+edge_persistent_kernel(EdgeLaunch L, PersistLaunch P) {
+  constexpr int NT = NW * 64;
+  constexpr int NB = Keys<PREC>::bins;
+  __shared__ uint32_t lds[NB];
+  __shared__ uint32_t tmp[NW];
+  __shared__ uint32_t s_task, s_flag;
+  int acq_view = -1;   // readiness this work-group has already acquired
+  uint32_t acq_level = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_task = atomicAdd(&P.ctl->queue, 1u);
+    __syncthreads();
+    // re-read per task: values derived from the task index or the thread
+    // index are recomputed inside each task instead of living across all
+    const uint32_t t = __builtin_amdgcn_readfirstlane(*(volatile uint32_t*)&s_task);
+    if (t >= (uint32_t)P.n_tasks) break;
+    const PTask tk = P.tasks[t];
+    const int v = tk.view;
+    PViewSync* sy = P.sync + v;
+    if (tk.type == kTaskStencil) {
+      const EdgeItem it = L.items[tk.idx];
+      const ViewDesc vd = L.views[v];
+      for (int i = threadIdx.x; i < NB; i += NT) lds[i] = 0;
+      __syncthreads();
+      const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+      const int ys = it.y0 + w * L.seg_rows;
+      const int ye = min(ys + L.seg_rows, it.y0 + it.rows);
+      if (ys < ye) wave_strip<PREC>(L, vd, it.x0, ys, ye, lds);
+      __syncthreads();
+      uint32_t* gh = L.hist + (int64_t)v * kBinsMax;
+      for (int i = threadIdx.x; i < NB; i += NT) {
+        const uint32_t c = lds[i];
+        if (c) atomicAdd(gh + i, c);
+      }
+      if (arrive<NW>(&sy->left[0], sy->n_items, &s_flag)) {
+        select_hist<PREC, NW>(L, v, tmp);
+        publish(&sy->ready, 1u);
+      }
+    } else {
+      const uint32_t need = (uint32_t)tk.phase;
+      if (acq_view != v || acq_level < need) {
+        await(&sy->ready, need, &P.ctl->error);
+        acq_view = v;
+        acq_level = need;
+      }
+      const FlatItem it = L.flat[tk.idx];
+      const MedState st = load_state(L.state + v);
+      if (tk.type == kTaskRefine) {
+        const int db = refine_digit_bits(PREC);
+        refine_chunk<PREC, NW>(L, it, st, db, lds);
+        if (arrive<NW>(&sy->left[tk.phase], sy->n_flat, &s_flag)) {
+          select_refine<NW>(L, v, db, tmp);
+          publish(&sy->ready, need + 1u);
+        }
+      } else {
+        norm_chunk<PREC, NW>(L, it, st.med);
+        if (arrive<NW>(&sy->left[tk.phase], sy->n_flat, &s_flag) && threadIdx.x == 0) st_agent(&sy->ready, 0u);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && atomicAdd(&P.ctl->exited, 1u) == gridDim.x - 1) {
+    st_agent(&P.ctl->queue, 0u);
+    st_agent(&P.ctl->exited, 0u);
+  }
+}
+
+template <int PREC>
+hipError_t persistent_for_prec(const EdgeLaunch& L, const PersistLaunch& P, int grid, hipStream_t s) {
+  switch (L.wg_waves) {
+    case 1: hipLaunchKernelGGL((edge_persistent_kernel<PREC, 1>), dim3(grid), dim3(64), 0, s, L, P); break;
+    case 2: hipLaunchKernelGGL((edge_persistent_kernel<PREC, 2>), dim3(grid), dim3(128), 0, s, L, P); break;
+    case 8: hipLaunchKernelGGL((edge_persistent_kernel<PREC, 8>), dim3(grid), dim3(512), 0, s, L, P); break;
+    default: hipLaunchKernelGGL((edge_persistent_kernel<PREC, 4>), dim3(grid), dim3(256), 0, s, L, P); break;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+int blocks_per_cu_for_prec(int wg_waves) {
+  int nb = 0;
+  hipError_t e;
+  switch (wg_waves) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_persistent_kernel<PREC, 1>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_persistent_kernel<PREC, 2>, 128, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_persistent_kernel<PREC, 8>, 512, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, edge_persistent_kernel<PREC, 4>, 256, 0); break;
+  }
+  return e == hipSuccess ? nb : 0;
 }
 
 template <int PREC>
@@ -519,9 +1009,30 @@ hipError_t launch_edge_fused(const EdgeLaunch& L, int item0, int n_items, hipStr
   }
 }
 
+hipError_t launch_edge_persistent(const EdgeLaunch& L, const PersistLaunch& P, int grid, hipStream_t s) {
+  if (grid <= 0 || P.n_tasks <= 0) return hipSuccess;
+  switch (L.precision) {
+    case IGSP_FP16: return persistent_for_prec<IGSP_FP16>(L, P, grid, s);
+    case IGSP_BF16: return persistent_for_prec<IGSP_BF16>(L, P, grid, s);
+    default: return persistent_for_prec<IGSP_FP32>(L, P, grid, s);
+  }
+}
+
+int persistent_blocks_per_cu(int precision, int wg_waves) {
+  switch (precision) {
+    case IGSP_FP16: return blocks_per_cu_for_prec<IGSP_FP16>(wg_waves);
+    case IGSP_BF16: return blocks_per_cu_for_prec<IGSP_BF16>(wg_waves);
+    default: return blocks_per_cu_for_prec<IGSP_FP32>(wg_waves);
+  }
+}
+
 hipError_t launch_median_select(const EdgeLaunch& L, int v0, int nv, hipStream_t s) {
   if (nv <= 0) return hipSuccess;
-  hipLaunchKernelGGL(median_select_kernel, dim3(nv), dim3(256), 0, s, L, v0);
+  switch (L.precision) {
+    case IGSP_FP16: hipLaunchKernelGGL(median_select_kernel<IGSP_FP16>, dim3(nv), dim3(256), 0, s, L, v0); break;
+    case IGSP_BF16: hipLaunchKernelGGL(median_select_kernel<IGSP_BF16>, dim3(nv), dim3(256), 0, s, L, v0); break;
+    default: hipLaunchKernelGGL(median_select_kernel<IGSP_FP32>, dim3(nv), dim3(256), 0, s, L, v0); break;
+  }
   return hipGetLastError();
 }
 

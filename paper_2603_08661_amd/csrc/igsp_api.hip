@@ -2,6 +2,9 @@
 // tables, work lists, median workspaces, intermediate maps), the launch
 // sequence of each form, and the graph-captured densification step.
 #include <algorithm>
+#include <cstdio>
+#include <string>
+#include <tuple>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -18,6 +21,11 @@ namespace igsp {
 namespace {
 
 constexpr int kFlatChunk = 16384;  // pixels per work-group of the element-wise passes
+constexpr int kPersistChunk = 65536;  // pixels per element-wise task of the persistent form
+// Distance, in tasks, between a view's phases in the persistent task list, as
+// a multiple of the resident work-groups: a task handed out that many
+// positions later finds the earlier phase finished.
+constexpr int kLagGenerations = 3;
 constexpr int kMaxPlans = 8;
 
 std::mutex g_mu;
@@ -76,9 +84,17 @@ struct EdgePlan {
   uint32_t* d_hist = nullptr;
   uint32_t* d_rhist = nullptr;
   MedState* d_state = nullptr;
+  // persistent form (built on first use): its own coarser flat chunks, the
+  // ordered task list, per-view phase counters and the queue
+  FlatItem* d_pflat = nullptr;
+  PTask* d_tasks = nullptr;
+  PViewSync* d_sync = nullptr;
+  PCtl* d_ctl = nullptr;
+  int n_tasks = 0, grid = 0, lag = 0;
   ~EdgePlan() {
     (void)hipFree(d_views); (void)hipFree(d_items); (void)hipFree(d_flat); (void)hipFree(d_map);
     (void)hipFree(d_hist); (void)hipFree(d_rhist); (void)hipFree(d_state);
+    (void)hipFree(d_pflat); (void)hipFree(d_tasks); (void)hipFree(d_sync); (void)hipFree(d_ctl);
   }
 };
 
@@ -86,6 +102,90 @@ std::list<std::shared_ptr<EdgePlan>> g_edge_plans;  // most recently used first
 
 int default_seg_rows() { return 64; }
 int default_wg_waves() { return 4; }
+
+// ------------------------------------------------------------------ tuning
+
+// Size class of a batch: tuned tile shapes apply to geometries in the same
+// class (device architecture, precision, form, total pixels and mean width
+// rounded to powers of two).
+struct TuneKey {
+  std::string arch;
+  int precision, batched, log2_px, log2_w;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(arch, precision, batched, log2_px, log2_w) <
+           std::tie(o.arch, o.precision, o.batched, o.log2_px, o.log2_w);
+  }
+};
+struct TuneVal {
+  int seg_rows, wg_waves, form;
+  double ms;
+};
+std::map<TuneKey, TuneVal> g_tuned;
+bool g_tune_loaded = false;
+
+int ilog2(int64_t v) {
+  int r = 0;
+  while (v > 1) { v >>= 1; ++r; }
+  return r;
+}
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+
+TuneKey tune_key(const igsp_view* views, int32_t n, int precision, int batched) {
+  int64_t px = 0, w = 0;
+  for (int i = 0; i < n; ++i) {
+    px += (int64_t)views[i].width * views[i].height;
+    w += views[i].width;
+  }
+  return TuneKey{device_arch(), precision, batched, ilog2(std::max<int64_t>(px, 1)),
+                 ilog2(std::max<int64_t>(w / std::max(n, 1), 1))};
+}
+
+// The cache file: one JSON object per line,
+// {"arch":"gfx950","precision":2,"batched":1,"log2_px":29,"log2_w":10,"seg_rows":64,"wg_waves":4,
+//  "form":3,"ms":1.3}
+void load_tune_cache() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("IGSP_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512], arch[64];
+  while (std::fgets(line, sizeof(line), f)) {
+    TuneKey k;
+    TuneVal v;
+    if (std::sscanf(line,
+                    " {\"arch\":\"%63[^\"]\",\"precision\":%d,\"batched\":%d,\"log2_px\":%d,\"log2_w\":%d,"
+                    "\"seg_rows\":%d,\"wg_waves\":%d,\"form\":%d,\"ms\":%lf",
+                    arch, &k.precision, &k.batched, &k.log2_px, &k.log2_w, &v.seg_rows, &v.wg_waves, &v.form,
+                    &v.ms) == 9) {
+      k.arch = arch;
+      g_tuned[k] = v;
+    }
+  }
+  std::fclose(f);
+}
+
+void save_tune_cache() {
+  const char* path = std::getenv("IGSP_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  for (const auto& kv : g_tuned)
+    std::fprintf(f,
+                 "{\"arch\":\"%s\",\"precision\":%d,\"batched\":%d,\"log2_px\":%d,\"log2_w\":%d,"
+                 "\"seg_rows\":%d,\"wg_waves\":%d,\"form\":%d,\"ms\":%.6f}\n",
+                 kv.first.arch.c_str(), kv.first.precision, kv.first.batched, kv.first.log2_px, kv.first.log2_w,
+                 kv.second.seg_rows, kv.second.wg_waves, kv.second.form, kv.second.ms);
+  std::fclose(f);
+}
 
 igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) {
   auto plan = std::make_shared<EdgePlan>();
@@ -118,7 +218,7 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
       upload(&plan->d_flat, flat) != hipSuccess)
     return IGSP_ERR_HIP;
   if (hipMalloc(&plan->d_map, (size_t)std::max<int64_t>(map_elems, 64) * esz) != hipSuccess) return IGSP_ERR_HIP;
-  const size_t hb = (size_t)n * kBins * sizeof(uint32_t), rb = (size_t)n * kRefineBins * sizeof(uint32_t);
+  const size_t hb = (size_t)n * kBinsMax * sizeof(uint32_t), rb = (size_t)n * kRefineBins * sizeof(uint32_t);
   if (hipMalloc(reinterpret_cast<void**>(&plan->d_hist), hb) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&plan->d_rhist), rb) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&plan->d_state), (size_t)n * sizeof(MedState)) != hipSuccess)
@@ -135,6 +235,75 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
   return IGSP_OK;
 }
 
+// Task list of the persistent form: phase p of view v is emitted at step
+// v + p * lag, so each phase follows the one before it by `lag` views of
+// other work (topological order: every task comes after what it waits for).
+igsp_status ensure_persistent(EdgePlan* P) {
+  if (P->d_tasks) return IGSP_OK;
+  const int n = P->n_views;
+  const int prec = P->key.precision;
+  const int levels = prec == IGSP_FP16 ? 1 : (prec == IGSP_FP32 ? 2 : 0);
+  const int phases = levels + 2;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return IGSP_ERR_HIP;
+  const int per_cu = persistent_blocks_per_cu(prec, P->key.wg_waves);
+  if (per_cu <= 0 || cus <= 0) return IGSP_ERR_HIP;
+  P->grid = per_cu * cus;
+  std::vector<FlatItem> pflat;
+  std::vector<int> pflat_begin(n + 1);
+  for (int v = 0; v < n; ++v) {
+    const int64_t npx = (int64_t)P->key.views[v].width * P->key.views[v].height;
+    pflat_begin[v] = (int)pflat.size();
+    for (int64_t p = 0; p < npx; p += kPersistChunk)
+      pflat.push_back(FlatItem{v, 0, p, std::min(npx, p + kPersistChunk)});
+  }
+  pflat_begin[n] = (int)pflat.size();
+  const int64_t per_view = ((int64_t)P->item_begin[n] + (int64_t)(phases - 1) * pflat_begin[n]) / std::max(n, 1);
+  P->lag = (int)std::min<int64_t>(std::max<int64_t>(1, ((int64_t)kLagGenerations * P->grid + per_view - 1) /
+                                                           std::max<int64_t>(per_view, 1)),
+                                  std::max(n, 1));
+  std::vector<PTask> tasks;
+  for (int k = 0; k < n + (phases - 1) * P->lag; ++k)
+    for (int p = 0; p < phases; ++p) {
+      const int v = k - p * P->lag;
+      if (v < 0 || v >= n) continue;
+      if (p == 0) {
+        for (int i = P->item_begin[v]; i < P->item_begin[v + 1]; ++i) tasks.push_back(PTask{kTaskStencil, v, i, 0});
+      } else {
+        const int type = p <= levels ? kTaskRefine : kTaskNorm;
+        for (int f = pflat_begin[v]; f < pflat_begin[v + 1]; ++f) tasks.push_back(PTask{type, v, f, p});
+      }
+    }
+  std::vector<PViewSync> sync(n);
+  for (int v = 0; v < n; ++v) {
+    const uint32_t ni = (uint32_t)(P->item_begin[v + 1] - P->item_begin[v]);
+    const uint32_t nf = (uint32_t)(pflat_begin[v + 1] - pflat_begin[v]);
+    sync[v] = PViewSync{{ni, nf, nf, nf}, 0u, ni, nf, 0u};
+  }
+  std::vector<PCtl> ctl(1, PCtl{0u, 0u, 0u, 0u});
+  P->n_tasks = (int)tasks.size();
+  if (upload(&P->d_pflat, pflat) != hipSuccess || upload(&P->d_sync, sync) != hipSuccess ||
+      upload(&P->d_ctl, ctl) != hipSuccess || upload(&P->d_tasks, tasks) != hipSuccess) {
+    (void)hipFree(P->d_pflat); (void)hipFree(P->d_sync); (void)hipFree(P->d_ctl); (void)hipFree(P->d_tasks);
+    P->d_pflat = nullptr; P->d_sync = nullptr; P->d_ctl = nullptr; P->d_tasks = nullptr;
+    return IGSP_ERR_HIP;
+  }
+  return IGSP_OK;
+}
+
+// The concrete form of a call: plain per view, staged batched, or one
+// persistent launch. IGSP_BATCHED lets the library choose (tuned, else
+// staged).
+int resolve_form(const igsp_view* views, int32_t n_views, const igsp_edge_opts* opts) {
+  const int b = opts ? opts->batched : IGSP_BATCHED;
+  if (b != IGSP_BATCHED) return b;
+  load_tune_cache();
+  auto it = g_tuned.find(tune_key(views, n_views, opts ? opts->precision : IGSP_FP32, IGSP_BATCHED));
+  return it != g_tuned.end() ? it->second.form : IGSP_BATCHED_STAGED;
+}
+
 igsp_status get_edge_plan(const igsp_view* views, int32_t n_views, const igsp_edge_opts* opts,
                           std::shared_ptr<EdgePlan>* out) {
   int dev = 0;
@@ -143,17 +312,29 @@ igsp_status get_edge_plan(const igsp_view* views, int32_t n_views, const igsp_ed
   EdgeKey key;
   key.device = dev;
   key.precision = opts ? opts->precision : IGSP_FP32;
-  key.seg_rows = (opts && opts->seg_rows) ? opts->seg_rows : default_seg_rows();
-  key.wg_waves = (opts && opts->wg_waves) ? opts->wg_waves : default_wg_waves();
+  int seg = default_seg_rows(), wgw = default_wg_waves();
+  if (!opts || (opts->seg_rows == 0 && opts->wg_waves == 0)) {
+    load_tune_cache();
+    auto it = g_tuned.find(tune_key(views, n_views, key.precision, opts ? opts->batched : IGSP_BATCHED));
+    if (it != g_tuned.end()) {
+      seg = it->second.seg_rows;
+      wgw = it->second.wg_waves;
+    }
+  }
+  key.seg_rows = (opts && opts->seg_rows) ? opts->seg_rows : seg;
+  key.wg_waves = (opts && opts->wg_waves) ? opts->wg_waves : wgw;
   key.views.assign(views, views + n_views);
+  const bool persistent = resolve_form(views, n_views, opts) == IGSP_BATCHED_PERSISTENT;
   for (auto it = g_edge_plans.begin(); it != g_edge_plans.end(); ++it) {
     if ((*it)->key == key) {
       g_edge_plans.splice(g_edge_plans.begin(), g_edge_plans, it);
       *out = g_edge_plans.front();
-      return IGSP_OK;
+      return persistent ? ensure_persistent(out->get()) : IGSP_OK;
     }
   }
-  return build_edge_plan(key, out);
+  st = build_edge_plan(key, out);
+  if (st == IGSP_OK && persistent) st = ensure_persistent(out->get());
+  return st;
 }
 
 igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, float* out_maps,
@@ -175,37 +356,58 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
   L.precision = P->key.precision;
   L.wg_waves = P->key.wg_waves;
   L.seg_rows = P->key.seg_rows;
-  const bool batched = !opts || opts->batched;
+  const int form = resolve_form(P->key.views.data(), P->n_views, opts);
+  const bool batched = form != IGSP_PLAIN;
   const int n = P->n_views;
   // refinement passes of the median's radix selection: (digit bits) per pass
   std::vector<int> passes;
   if (L.precision == IGSP_FP16) passes = {3};
   else if (L.precision == IGSP_FP32) passes = {8, 8};
   hipEvent_t* ev = L.stage_events;
-  auto mark = [&](int k, bool on) -> hipError_t {
-    return (ev && on) ? hipEventRecord(ev[k], s) : hipSuccess;
-  };
-  auto run = [&](int v0, int v1, bool marks) -> hipError_t {
-    const int i0 = P->item_begin[v0], i1 = P->item_begin[v1];
+  auto mark = [&](int k, hipStream_t st) -> hipError_t { return ev ? hipEventRecord(ev[k], st) : hipSuccess; };
+  // median selection (+ refinement passes) and normalisation of views [v0, v1)
+  auto tail = [&](int v0, int v1, hipStream_t st) -> hipError_t {
     const int f0 = P->flat_begin[v0], f1 = P->flat_begin[v1];
-    hipError_t e = launch_edge_fused(L, i0, i1 - i0, s);
-    if (e == hipSuccess) e = mark(1, marks);
-    if (e == hipSuccess) e = launch_median_select(L, v0, v1 - v0, s);
+    hipError_t e = launch_median_select(L, v0, v1 - v0, st);
     for (int db : passes) {
-      if (e == hipSuccess) e = launch_median_refine(L, f0, f1 - f0, db, s);
-      if (e == hipSuccess) e = launch_refine_select(L, v0, v1 - v0, db, 0, s);
+      if (e == hipSuccess) e = launch_median_refine(L, f0, f1 - f0, db, st);
+      if (e == hipSuccess) e = launch_refine_select(L, v0, v1 - v0, db, 0, st);
     }
-    if (e == hipSuccess) e = mark(2, marks);
-    if (e == hipSuccess) e = launch_normalise(L, f0, f1 - f0, s);
-    if (e == hipSuccess) e = mark(3, marks);
     return e;
   };
-  hipError_t e = mark(0, true);
-  if (e == hipSuccess && batched) {
-    e = run(0, n, true);
+  auto stencil = [&](int v0, int v1, hipStream_t st) -> hipError_t {
+    return launch_edge_fused(L, P->item_begin[v0], P->item_begin[v1] - P->item_begin[v0], st);
+  };
+  auto norm = [&](int v0, int v1, hipStream_t st) -> hipError_t {
+    return launch_normalise(L, P->flat_begin[v0], P->flat_begin[v1] - P->flat_begin[v0], st);
+  };
+  hipError_t e = mark(0, s);
+  if (e == hipSuccess && form == IGSP_BATCHED_PERSISTENT) {
+    if (!P->d_tasks) return IGSP_ERR_HIP;  // tables are built with the plan
+    PersistLaunch PL;
+    PL.tasks = P->d_tasks;
+    PL.sync = P->d_sync;
+    PL.ctl = P->d_ctl;
+    PL.n_tasks = P->n_tasks;
+    PL.levels = (int)passes.size();
+    EdgeLaunch LP = L;
+    LP.flat = P->d_pflat;
+    e = launch_edge_persistent(LP, PL, P->grid, s);
+    for (int k = 1; k < 4 && e == hipSuccess; ++k) e = mark(k, s);
+  } else if (e == hipSuccess && batched) {
+    e = stencil(0, n, s);
+    if (e == hipSuccess) e = mark(1, s);
+    if (e == hipSuccess) e = tail(0, n, s);
+    if (e == hipSuccess) e = mark(2, s);
+    if (e == hipSuccess) e = norm(0, n, s);
+    if (e == hipSuccess) e = mark(3, s);
   } else if (e == hipSuccess) {
-    for (int v = 0; v < n && e == hipSuccess; ++v) e = run(v, v + 1, false);
-    for (int k = 1; k < 4 && e == hipSuccess; ++k) e = mark(k, true);
+    for (int v = 0; v < n && e == hipSuccess; ++v) {
+      e = stencil(v, v + 1, s);
+      if (e == hipSuccess) e = tail(v, v + 1, s);
+      if (e == hipSuccess) e = norm(v, v + 1, s);
+    }
+    for (int k = 1; k < 4 && e == hipSuccess; ++k) e = mark(k, s);
   }
   return e == hipSuccess ? IGSP_OK : IGSP_ERR_HIP;
 }
@@ -293,6 +495,69 @@ extern "C" igsp_status long_axis_split(const igsp_gaussians* g, const uint8_t* m
   st = get_las_plan(g->capacity, &plan);
   if (st != IGSP_OK) return st;
   return enqueue_las(plan.get(), g, mask, out, params, static_cast<hipStream_t>(stream));
+}
+
+extern "C" igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view* views, int32_t n_views,
+                                          float* out_maps, int32_t precision, int32_t batched,
+                                          igsp_edge_opts* best, void* stream) {
+  igsp_edge_opts base{precision, batched, 0, 0, nullptr, nullptr, nullptr};
+  EdgeExtent ext{};
+  igsp_status st = validate_edge(images, views, n_views, out_maps, &base, &ext);
+  if (st != IGSP_OK) return st;
+  if (n_views == 0) return IGSP_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  static const int kSeg[] = {32, 48, 64, 96, 128};
+  static const int kWaves[] = {1, 2, 4, 8};
+  std::vector<int> forms;
+  if (batched == IGSP_BATCHED) forms = {IGSP_BATCHED_STAGED, IGSP_BATCHED_PERSISTENT};
+  else forms = {batched};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return IGSP_ERR_HIP;
+  }
+  TuneVal bestv{default_seg_rows(), default_wg_waves(), forms.back(), 1e30};
+  for (int seg : kSeg)
+    for (int wgw : kWaves)
+      for (int form : forms) {
+        if (st != IGSP_OK) break;
+        igsp_edge_opts o = base;
+        o.batched = form;
+        o.seg_rows = seg;
+        o.wg_waves = wgw;
+        std::shared_ptr<EdgePlan> plan;
+        {
+          std::lock_guard<std::mutex> lk(g_mu);
+          st = get_edge_plan(views, n_views, &o, &plan);
+        }
+        if (st != IGSP_OK) break;
+        const int reps = 3;
+        st = enqueue_edge(plan.get(), images, ext.img_end, out_maps, &o, s);  // warm-up
+        if (st == IGSP_OK && hipEventRecord(e0, s) != hipSuccess) st = IGSP_ERR_HIP;
+        for (int r = 0; r < reps && st == IGSP_OK; ++r)
+          st = enqueue_edge(plan.get(), images, ext.img_end, out_maps, &o, s);
+        if (st == IGSP_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+          st = IGSP_ERR_HIP;
+        float ms = 0.0f;
+        if (st == IGSP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = IGSP_ERR_HIP;
+        if (st == IGSP_OK && ms / reps < bestv.ms) bestv = TuneVal{seg, wgw, form, ms / reps};
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != IGSP_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_tune_cache();
+    g_tuned[tune_key(views, n_views, precision, batched)] = bestv;
+    save_tune_cache();
+  }
+  if (best) {
+    *best = base;
+    best->batched = bestv.form;
+    best->seg_rows = bestv.seg_rows;
+    best->wg_waves = bestv.wg_waves;
+  }
+  return IGSP_OK;
 }
 
 struct igsp_step {

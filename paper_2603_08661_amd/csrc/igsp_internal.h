@@ -20,17 +20,23 @@ constexpr int kLanePx = 4;
 constexpr int kWaveCols = 64 * kLanePx;       // 256
 constexpr int kHalo = 4;
 constexpr int kStripCols = kWaveCols - 2 * kHalo;  // 248
-constexpr int kStageBytes = 1024;              // per-wave LDS row staging
 
-// Survivor magnitudes are stored as sqrt(M) * 2^-13 (M the exact squared
-// unnormalised Sobel magnitude, 1 <= M < 2^57 for 8-bit input): the scale
-// keeps every value inside the normal range of FP16 and cancels in the
-// normalisation. The median is found by radix selection on the bit pattern
-// of the stored value widened to float32: the first histogram resolves the
-// top 16 bits, whose possible range for survivors is [kKeyLo, kKeyLo+kBins).
-constexpr float kStoreScale = 1.0f / 8192.0f;
-constexpr uint32_t kKeyLo = 114u * 128u;  // float32 exponent 114 = 2^-13
-constexpr int kBins = 30 * 128;           // 30 binades x 7 mantissa bits
+// What the stencil pass stores for a surviving pixel, from the exact squared
+// unnormalised Sobel magnitude M (1 <= M < 2^57 for 8-bit input):
+//   FP16 storage : q = sqrt(M) * 2^-13, inside FP16's normal range;
+//   FP32 / BF16  : q = M itself (no root in the stencil; the normalisation
+//                  takes sqrt(q / median), which also halves BF16's rounding).
+// Both are monotone in M, so the lower median of q is the q of the median
+// magnitude. The median is found by radix selection on the bit pattern of
+// q widened to float32; the first histogram resolves the top 16 bits
+// (exponent + 7 mantissa bits), whose possible range for survivors is
+// [key_lo, key_lo + bins).
+constexpr float kStoreScaleRoot = 1.0f / 8192.0f;          // 2^-13
+constexpr uint32_t kKeyLoRoot = 114u * 128u;               // float32 exponent of 2^-13
+constexpr int kBinsRoot = 30 * 128;                        // 2^-13 .. 2^17
+constexpr uint32_t kKeyLoSquare = 127u * 128u;             // float32 exponent of 1
+constexpr int kBinsSquare = 58 * 128;                      // 1 .. 2^58
+constexpr int kBinsMax = kBinsSquare;
 constexpr int kRefineBins = 256;          // radix digit of the refine passes
 
 struct ViewDesc {
@@ -70,7 +76,7 @@ struct EdgeLaunch {
   const EdgeItem* items;
   const FlatItem* flat;
   void* map;
-  uint32_t* hist;            // [n_views][kBins]
+  uint32_t* hist;            // [n_views][kBinsMax]
   uint32_t* rhist;           // [n_views][kRefineBins]
   MedState* state;           // [n_views]
   float* medians_dn;         // optional outputs
@@ -81,6 +87,43 @@ struct EdgeLaunch {
   int seg_rows;
 };
 
+// Work list of the single persistent launch of the batched form. Phases of
+// a view: 0 = stencil items, 1..levels = refinement passes of the median's
+// radix selection, levels + 1 = normalisation; each later phase waits for
+// the selection step that closes the phase before it.
+enum : int32_t { kTaskStencil = 0, kTaskRefine = 1, kTaskNorm = 2 };
+
+struct PTask {
+  int32_t type;
+  int32_t view;
+  int32_t idx;       // stencil: index into items; refine / norm: into flat
+  int32_t phase;     // 0 .. levels + 1
+};
+
+struct PViewSync {   // per view, in device memory
+  uint32_t left[4];  // tasks of each phase still running; the last one
+                     // restores the count for the next launch
+  uint32_t ready;    // selection steps completed (reset to 0 at the end)
+  uint32_t n_items;  // restore values: stencil items, flat chunks
+  uint32_t n_flat;
+  uint32_t pad;
+};
+
+struct PCtl {        // whole launch, in device memory
+  uint32_t queue;    // next task to hand out
+  uint32_t exited;   // work-groups that found the queue empty
+  uint32_t error;    // bit 0: a wait exceeded its spin limit
+  uint32_t pad;
+};
+
+struct PersistLaunch {
+  const PTask* tasks;
+  PViewSync* sync;
+  PCtl* ctl;
+  int32_t n_tasks;
+  int32_t levels;    // refinement passes: BF16 0, FP16 1, FP32 2
+};
+
 // Enqueue each stage over the given ranges (item ranges index the plan's
 // tables; view ranges are [v0, v1)).
 hipError_t launch_edge_fused(const EdgeLaunch& L, int item0, int n_items, hipStream_t s);
@@ -89,6 +132,10 @@ hipError_t launch_median_refine(const EdgeLaunch& L, int flat0, int n_flat, int 
 hipError_t launch_refine_select(const EdgeLaunch& L, int v0, int nv, int digit_bits, int final_shift,
                                 hipStream_t s);
 hipError_t launch_normalise(const EdgeLaunch& L, int flat0, int n_flat, hipStream_t s);
+// The whole batched pipeline as one launch of `grid` persistent work-groups.
+hipError_t launch_edge_persistent(const EdgeLaunch& L, const PersistLaunch& P, int grid, hipStream_t s);
+// Work-groups of the persistent kernel resident per compute unit.
+int persistent_blocks_per_cu(int precision, int wg_waves);
 
 // ---------------------------------------------------------------- LAS
 

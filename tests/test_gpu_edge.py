@@ -15,6 +15,7 @@ from parity import check_batch, compare_view, gpu_edge, view_map
 pytestmark = pytest.mark.gpu
 
 PRECS = ["fp32", "fp16", "bf16"]
+BATCHED_FORMS = ["staged", "persistent"]
 
 
 def small_batch(in_align=1, out_align=1):
@@ -29,22 +30,24 @@ def small_batch(in_align=1, out_align=1):
 def test_workload1_single_view(precision):
     w = synth.workload(1)
     vb = w.render(in_align=256, out_align=64)
-    for batched in (True, False):
-        st = check_batch(vb, precision, batched)
-        print(precision, batched, st)
+    for form in ("plain", "staged", "persistent"):
+        st = check_batch(vb, precision, form)
+        print(precision, form, st)
 
 
+@pytest.mark.parametrize("form", BATCHED_FORMS)
 @pytest.mark.parametrize("precision", PRECS)
-def test_ragged_views_unaligned(precision):
+def test_ragged_views_unaligned(precision, form):
     vb = small_batch()
-    st = check_batch(vb, precision, True)
-    print(precision, sum(s["mismatch"] for s in st), max(s["scaled_err"] for s in st))
+    st = check_batch(vb, precision, form)
+    print(precision, form, sum(s["mismatch"] for s in st), max(s["scaled_err"] for s in st))
 
 
+@pytest.mark.parametrize("form", BATCHED_FORMS)
 @pytest.mark.parametrize("seg_rows,wg_waves", [(8, 1), (16, 2), (32, 4), (64, 8), (128, 4), (24, 2)])
-def test_tile_shapes(seg_rows, wg_waves):
+def test_tile_shapes(seg_rows, wg_waves, form):
     vb = small_batch(in_align=16, out_align=4)
-    check_batch(vb, "fp32", True, seg_rows=seg_rows, wg_waves=wg_waves)
+    check_batch(vb, "fp32", form, seg_rows=seg_rows, wg_waves=wg_waves)
 
 
 def test_adversarial_images():
@@ -64,7 +67,8 @@ def test_adversarial_images():
     imgs.append(np.random.default_rng(1).integers(100, 103, (H, W, 3), dtype=np.uint8))
     vb = synth.pack_views(imgs, in_align=1, out_align=1)
     for p in PRECS:
-        check_batch(vb, p, True)
+        for form in BATCHED_FORMS:
+            check_batch(vb, p, form)
 
 
 def test_step_edge_ridge_exact():
@@ -77,13 +81,15 @@ def test_step_edge_ridge_exact():
 
 
 @pytest.mark.parametrize("precision", PRECS)
-def test_batched_equals_plain_and_deterministic(precision):
+def test_forms_equal_and_deterministic(precision):
+    """Every launch form gives the same bits; repeated calls reuse the plan
+    (whose counters, histograms and queue each call restores)."""
     vb = small_batch(in_align=16, out_align=4)
-    a = gpu_edge(vb, precision, True)
-    b = gpu_edge(vb, precision, False)
-    c = gpu_edge(vb, precision, True, reps=3)       # repeated calls reuse the plan
-    for x, y in ((a, b), (a, c)):
-        for u, v in zip(x, y):
+    a = gpu_edge(vb, precision, "staged")
+    others = [gpu_edge(vb, precision, "plain"), gpu_edge(vb, precision, "persistent"),
+              gpu_edge(vb, precision, "persistent", reps=4), gpu_edge(vb, precision, "staged", reps=3)]
+    for y in others:
+        for u, v in zip(a, y):
             assert (u == v).all()
 
 
@@ -100,23 +106,26 @@ def test_permuting_views_permutes_outputs():
 def test_workload2_full_oracle():
     w = synth.workload(2)
     vb = w.render(in_align=256, out_align=64)
-    for p in PRECS:
-        st = check_batch(vb, p, p != "fp32")
-        print("workload2", p, st)
+    for p, form in zip(PRECS, ("plain", "staged", "persistent")):
+        st = check_batch(vb, p, form)
+        print("workload2", p, form, st)
 
 
 @pytest.mark.parametrize("c,precisions,sample", [(3, ["fp16", "fp32"], [0, 57, 199]),
                                                  (4, ["fp16", "bf16"], [0, 1, 148, 149]),
                                                  (5, ["bf16"], [0, 150, 299])])
 def test_full_size_workloads_sampled(c, precisions, sample):
-    """Every view of the full workload goes through one batched launch per
-    stage; sampled views are checked against the oracle pixel by pixel."""
+    """Every view of the full workload goes through one persistent launch (the
+    form the benchmark times); sampled views are checked against the oracle
+    pixel by pixel, and the staged form must give the same bits."""
     w = synth.workload(c)
     vb = w.render()
+    refs = {v: oracle.edge_view(vb.view(v)) for v in sample}
     for p in precisions:
-        E, med, nsv = gpu_edge(vb, p, True)
+        E, med, nsv = gpu_edge(vb, p, "persistent")
         for v in sample:
-            ref = oracle.edge_view(vb.view(v))
-            st = compare_view(view_map(E, vb, v), ref, p, med[v], nsv[v])
+            st = compare_view(view_map(E, vb, v), refs[v], p, med[v], nsv[v])
             print(f"workload{c} {p} view {v}", st)
         assert (nsv > 0).all() and (med > 0).all()
+        E2, med2, nsv2 = gpu_edge(vb, p, "staged")
+        assert (E2 == E).all() and (med2 == med).all() and (nsv2 == nsv).all()

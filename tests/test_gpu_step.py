@@ -35,8 +35,9 @@ def _setup(precision):
     return vb, img, views, fresh, torch.from_numpy(mk).to(dev), cap
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp32"])
-def test_graph_replays_equal_eager(precision):
+@pytest.mark.parametrize("precision,form", [("bf16", "persistent"), ("fp32", "persistent"), ("bf16", "staged"),
+                                            ("fp16", "persistent")])
+def test_graph_replays_equal_eager(precision, form):
     import torch
 
     import paper_2603_08661_amd as igsp
@@ -48,7 +49,7 @@ def test_graph_replays_equal_eager(precision):
     out_a = torch.zeros(vb.out_floats, dtype=torch.float32, device=dev)
     sidx_a = torch.full((cap,), -1, dtype=torch.int32, device=dev)
     st_a = torch.zeros(1, dtype=torch.int32, device=dev)
-    igsp.edge_importance(img, views, out_a, precision=precision)
+    igsp.edge_importance(img, views, out_a, precision=precision, batched="staged")
     igsp.long_axis_split(ga["means"], ga["log_scales"], ga["quats"], ga["opacity_logits"], ga["count"], mask,
                          sidx_a, st_a)
     torch.cuda.synchronize()
@@ -59,7 +60,7 @@ def test_graph_replays_equal_eager(precision):
     sidx_b = torch.full((cap,), -1, dtype=torch.int32, device=dev)
     st_b = torch.zeros(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.Stream()
-    step = igsp.Step(img, views, out_b, gb, mask, sidx_b, st_b, precision=precision, stream=stream)
+    step = igsp.Step(img, views, out_b, gb, mask, sidx_b, st_b, precision=precision, batched=form, stream=stream)
     for rep in range(3):
         with torch.cuda.stream(stream):
             for k in gb:
