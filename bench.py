@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edge-map megapixels/s + Gaussians split/s, batched-FP16 vs plain-FP32, % HBM peak"
 HBM_PEAK_GBS = 8000.0
+COPY_CAL_BYTES = 1 << 30
 STORE_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
 
 
@@ -55,6 +56,98 @@ def copy_calibration(nbytes: int):
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
+def _csv_rows(path_glob: str):
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(path_glob, recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _counter_kib(rows, name_part: str, counter: str):
+    """Mean per-dispatch value (KiB) of a counter over dispatches whose kernel
+    name contains name_part, and the number of dispatches."""
+    vals = [float(r["Counter_Value"]) for r in rows
+            if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def summarise_profile(d: str, copy_bytes: int):
+    """Turn the rocprofv3 outputs under directory d (trace/, fetch/, write/,
+    copy_fetch/, copy_write/ and bench.json, see the commands recorded in the
+    summaries) into the two short summaries kept under profiles/."""
+    import hashlib
+
+    res = json.loads(open(os.path.join(d, "bench.json")).read().strip().splitlines()[-1])
+    kernel = res["roofline"]["kernel"]
+    sym = {"edge_fused": "edge_fused_kernel", "edge_persistent": "edge_persistent_kernel"}[kernel]
+    stats = _csv_rows(os.path.join(d, "trace", "**", "*kernel_stats.csv"))
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    wl = res["config"]["workload"]
+    tag = f"{kernel}_w{res['config']['views']}v_{res['config']['intermediate']}"
+    bench_cmd = "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline"
+    lines = [f"# Kernel trace: {wl}", "",
+             "Command (repo root, TMPDIR=/tmp):", "",
+             f"    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/trace -o t -- {bench_cmd}"
+             " > <dir>/bench.json", "",
+             f"Benchmark line of that run: form `{res['config']['form']}`, tile {res['config']['tile']}, "
+             f"{res['ms_per_step']} ms/step; live HIP-event time of `{kernel}`: {res['stage_ms']['fused']} ms.", "",
+             "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share |", "|---|---|---|---|---|---|"]
+    total = sum(float(r["TotalDurationNs"]) for r in stats) or 1.0
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+        nm = r["Name"].replace("igsp::(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        nm = nm if len(nm) < 70 else nm[:67] + "..."
+        lines.append(f"| `{nm}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / total:.1f}% |")
+    avg = [float(r["AverageNs"]) for r in stats if sym in r["Name"]]
+    if avg:
+        lines += ["", f"`{kernel}` average over the trace: {avg[0] / 1e6:.4f} ms; the benchmark's live "
+                      f"measurement: {res['stage_ms']['fused']} ms."]
+    open(os.path.join(ROOT, "profiles", f"{tag}_kernel_trace.md"), "w").write("\n".join(lines) + "\n")
+
+    fetch, nf = _counter_kib(_csv_rows(os.path.join(d, "fetch", "**", "*counter_collection.csv")), sym, "FETCH_SIZE")
+    write, nw = _counter_kib(_csv_rows(os.path.join(d, "write", "**", "*counter_collection.csv")), sym, "WRITE_SIZE")
+    cf, _ = _counter_kib(_csv_rows(os.path.join(d, "copy_fetch", "**", "*counter_collection.csv")), "copy",
+                         "FETCH_SIZE")
+    cw, _ = _counter_kib(_csv_rows(os.path.join(d, "copy_write", "**", "*counter_collection.csv")), "copy",
+                         "WRITE_SIZE")
+    f_fetch = copy_bytes / (cf * 1024) if cf else None
+    f_write = copy_bytes / (cw * 1024) if cw else None
+    traffic = (fetch * 1024 * f_fetch + write * 1024 * f_write) if None not in (fetch, write, f_fetch, f_write) \
+        else None
+    src = os.path.join(ROOT, "paper_2603_08661_amd", "csrc", "edge_kernels.hip")
+    pmc_cmd = "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --stage-reps 2"
+    t = [f"kernel: {kernel}",
+         f"kernel_source_sha256: {hashlib.sha256(open(src, 'rb').read()).hexdigest()}",
+         f"workload: {wl}",
+         f"precision: {res['config']['intermediate']}",
+         f"tile: {res['config']['tile']}",
+         f"fetch_kib_per_dispatch: {fetch} ({nf} dispatches)",
+         f"write_kib_per_dispatch: {write} ({nw} dispatches)",
+         f"copy_calibration_bytes: {copy_bytes}",
+         f"copy_fetch_kib: {cf}", f"copy_write_kib: {cw}",
+         f"fetch_scale: {f_fetch}", f"write_scale: {f_write}",
+         f"traffic_bytes_per_launch: {traffic}",
+         f"algorithmic_bytes_per_launch: {res['roofline']['bytes_per_launch']}",
+         "",
+         "  Commands (repo root, TMPDIR=/tmp), each pass in its own run:",
+         f"    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o p -- {pmc_cmd}",
+         f"    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/write -o p -- {pmc_cmd}",
+         f"    timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/copy_fetch -o p -- "
+         f"python3 bench.py --copy-calibration {copy_bytes}",
+         f"    timeout -s KILL 60 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/copy_write -o p -- "
+         f"python3 bench.py --copy-calibration {copy_bytes}",
+         "    python3 bench.py --summarise-profile <dir>",
+         "  FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by copy_bytes / (1024 x what the same",
+         "  counter reads for the plain copy of copy_bytes bytes). traffic = scaled fetch + scaled write."]
+    open(os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic.txt"), "w").write("\n".join(t) + "\n")
+    print(json.dumps({"kernel": kernel, "traffic_bytes_per_launch": traffic, "trace_avg_ms":
+                      avg[0] / 1e6 if avg else None, "live_ms": res["stage_ms"]["fused"]}))
+
+
 def traffic_from_profile(kernel: str, prec: str, workload: str, seg_rows: int, wg_waves: int):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when that summary was taken on another kernel source,
@@ -74,7 +167,7 @@ def traffic_from_profile(kernel: str, prec: str, workload: str, seg_rows: int, w
                 or kv.get("workload") != workload or kv.get("tile") != f"{seg_rows}x{wg_waves}"):
             return None
         return int(float(kv["traffic_bytes_per_launch"]))
-    except (OSError, KeyError, ValueError):
+    except (OSError, KeyError, ValueError, TypeError):
         return None
 
 
@@ -91,14 +184,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     ap.add_argument("--stage-reps", type=int, default=10)
-    ap.add_argument("--no-tune", action="store_true", help="use the library's default tile shape")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner on this batch first (default: the library's tuned table)")
     ap.add_argument("--form", default="batched", choices=["batched", "staged", "persistent"],
                     help="batched launch form (batched: autotuned between staged and persistent)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (counter calibration)")
+    ap.add_argument("--summarise-profile", default=None, metavar="DIR",
+                    help="only summarise rocprofv3 outputs under DIR into profiles/")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.summarise_profile:
+        summarise_profile(args.summarise_profile, COPY_CAL_BYTES)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
@@ -168,16 +267,13 @@ def main():
 
     # ---- launch form and tile shape: explicit, the library default, or
     #      autotuned on this batch
-    seg, wgw, bform = args.seg_rows, args.wg_waves, args.form
-    if seg == 0 and wgw == 0 and not args.no_tune:
+    if args.tune and args.seg_rows == 0 and args.wg_waves == 0:
         t1 = time.time()
-        seg, wgw, bform = igsp.edge_autotune(img, views, out, precision=prec, batched=args.form, stream=stream)
+        igsp.edge_autotune(img, views, out, precision=prec, batched=args.form, stream=stream)
         torch.cuda.synchronize()
-        log(f"autotuned: form={bform} seg_rows={seg} wg_waves={wgw} ({time.time() - t1:.2f}s)")
-    elif seg == 0 and wgw == 0:
-        seg, wgw = 64, 4
-    if bform == "batched":
-        bform = "persistent"
+        log(f"autotuned in {time.time() - t1:.2f}s")
+    bform, seg, wgw = igsp.edge_resolve(views, prec, args.form, args.seg_rows, args.wg_waves)
+    log(f"form={bform} seg_rows={seg} wg_waves={wgw}")
     args.seg_rows, args.wg_waves = seg, wgw
 
     # ---- primary form: batched, reduced-precision storage, graph-captured step

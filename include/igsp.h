@@ -147,6 +147,17 @@ igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view* views, in
                                float* out_maps, int32_t precision, int32_t batched,
                                igsp_edge_opts* best, void* stream);
 
+/*
+ * The launch form and tile shape edge_importance would use for these views
+ * and options: on return opts->batched holds the concrete igsp_form and
+ * seg_rows / wg_waves are filled in (explicit values are kept; zeros become
+ * the tuned entry of the size class, else the defaults 64 x 4). Tuned entries
+ * come from the file IGSP_TUNE_DEFAULTS names (the shipped table, read only)
+ * and then IGSP_TUNE_CACHE (the autotuner's output), read once per process.
+ * opts (host, in/out). Touches no device memory and enqueues nothing.
+ */
+igsp_status igsp_edge_resolve(const igsp_view* views, int32_t n_views, igsp_edge_opts* opts);
+
 /* ------------------------------------------------------------------------ */
 /* Long-Axis-Split (Sec. 2.2, Algorithms 1 and 2)                            */
 /* ------------------------------------------------------------------------ */

@@ -25,8 +25,13 @@ STATUS = {
 }
 
 # Every symbol include/igsp.h declares.
-EXPORTS = ("edge_importance", "long_axis_split", "igsp_edge_autotune", "igsp_step_create", "igsp_step_launch",
-           "igsp_step_destroy", "igsp_status_string", "igsp_release_plans", "igsp_version")
+EXPORTS = ("edge_importance", "long_axis_split", "igsp_edge_autotune", "igsp_edge_resolve", "igsp_step_create",
+           "igsp_step_launch", "igsp_step_destroy", "igsp_status_string", "igsp_release_plans", "igsp_version")
+
+# Tile shapes and launch forms the autotuner picked on MI355X for the
+# benchmark geometries; the library reads this table unless the caller's
+# environment names another.
+TUNED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned", "gfx950.jsonl")
 
 
 class IgspError(RuntimeError):
@@ -75,6 +80,7 @@ def lib():
         # that this library binds to the runtime torch's tensors and streams use.
         import torch  # noqa: F401
 
+        os.environ.setdefault("IGSP_TUNE_DEFAULTS", TUNED_TABLE)
         L = ctypes.CDLL(LIB_PATH)
         vp, i32 = ctypes.c_void_p, ctypes.c_int32
         L.edge_importance.argtypes = [vp, ctypes.POINTER(View), i32, vp, ctypes.POINTER(EdgeOpts), vp]
@@ -84,6 +90,8 @@ def lib():
         L.long_axis_split.restype = i32
         L.igsp_edge_autotune.argtypes = [vp, ctypes.POINTER(View), i32, vp, i32, i32, ctypes.POINTER(EdgeOpts), vp]
         L.igsp_edge_autotune.restype = i32
+        L.igsp_edge_resolve.argtypes = [ctypes.POINTER(View), i32, ctypes.POINTER(EdgeOpts)]
+        L.igsp_edge_resolve.restype = i32
         L.igsp_step_create.argtypes = [vp, ctypes.POINTER(View), i32, vp, ctypes.POINTER(EdgeOpts),
                                        ctypes.POINTER(Gaussians), vp, ctypes.POINTER(LasOut),
                                        ctypes.POINTER(LasParams), vp, ctypes.POINTER(vp)]
@@ -235,6 +243,15 @@ def edge_autotune(images, views, out_maps, precision="fp32", batched=True, strea
     _check(lib().igsp_edge_autotune(_ptr(images), tab, n, _ptr(out_maps), p, form_code(batched),
                                     ctypes.byref(best), _stream(stream)), "igsp_edge_autotune")
     return int(best.seg_rows), int(best.wg_waves), FORM_NAMES[int(best.batched)]
+
+
+def edge_resolve(views, precision="fp32", batched=True, seg_rows=0, wg_waves=0):
+    """(form name, seg_rows, wg_waves) that edge_importance would use."""
+    tab, n = view_table(*views)
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o = EdgeOpts(p, form_code(batched), int(seg_rows), int(wg_waves), None, None, None)
+    _check(lib().igsp_edge_resolve(tab, n, ctypes.byref(o)), "igsp_edge_resolve")
+    return FORM_NAMES[int(o.batched)], int(o.seg_rows), int(o.wg_waves)
 
 
 def gaussians_struct(means, log_scales, quats, opacity_logits, count, features=None):

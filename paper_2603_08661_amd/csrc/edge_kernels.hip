@@ -203,9 +203,11 @@ struct StripState {
   Lane12 rows[2];                  // raw bytes: this row / next row
   int h[2][4], s1[2][4], s2[2][4], s3[2][4];   // vertical (1 1)^4 cascade
   int sx[2][4], u1[2][4];          // gx cascade
-  int bprev[2][4], d[2][4];        // gy: d(r) = b(r) - b(r-1), sy = d(r) + d(r-1)
+  int bprev[2][4];                 // blurred rows r-1 (other parity) and r-2 (same parity)
   float M[2][4];                   // squared magnitude, last two rows
-  float Mpp[4];                    // and the row before
+  float ML[2], MR[2];              // and the lanes' outer neighbours of each
+  float Mpp[4];                    // the row before them
+  float MppL, MppR;
   float fx[2][4], fy[2][4];        // gradient of the last two rows (exact in float for |g| < 2^24,
                                    // else rounded; only its orientation is read back)
 };
@@ -228,6 +230,13 @@ struct StripCtx {
 // dropped by the hardware, so every lane can issue the same stores.
 constexpr int kDropOffset = 0x40000000;
 
+// Cache policy of buffer accesses: 0 = default; kCpolAgent = device-coherent
+// (the SC1 scope bit, the same encoding the compiler gives agent-scope
+// relaxed atomic loads and stores): such stores are visible device-wide once
+// they complete, and such loads never return a stale line from another XCD's
+// L2, with no cache write-back or invalidation around them.
+constexpr int kCpolAgent = 16;
+
 template <bool NARROW>
 __device__ __forceinline__ Lane12 fetch_row(const StripCtx& C, int yy) {
   const __amdgpu_buffer_rsrc_t row = buffer_rsrc(C.img + fold_near(yy, C.H) * C.pitch, 3 * C.W);
@@ -235,7 +244,7 @@ __device__ __forceinline__ Lane12 fetch_row(const StripCtx& C, int yy) {
   else return load_lane(row, C.win_off);
 }
 
-template <int PREC, bool NARROW, bool ALIGNED, int P>
+template <int PREC, bool NARROW, bool ALIGNED, int P, int CPOL>
 __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int t, uint32_t* hist) {
   using St = Store<PREC>;
   constexpr int Q = P ^ 1;  // previous row's slot
@@ -285,21 +294,22 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   for (int i = 0; i < 4; ++i) {
     S.u1[P][i] = S.sx[P][i] + S.sx[Q][i];
     gx[i] = S.u1[P][i] + S.u1[Q][i];
-    S.d[P][i] = b[i] - S.bprev[Q][i];
+    sy[i] = b[i] - S.bprev[P][i];     // the same parity slot still holds b(r-2)
     S.bprev[P][i] = b[i];
-    sy[i] = S.d[P][i] + S.d[Q][i];
   }
   const int syL = from_left(sy[3]), syR = from_right(sy[0]);
   const int gy[4] = {syL + 2 * sy[0] + sy[1], sy[0] + 2 * sy[1] + sy[2], sy[1] + 2 * sy[2] + sy[3],
                      sy[2] + 2 * sy[3] + syR};
 
-  // ---- 5. squared magnitude of row yy-3
+  // ---- 5. squared magnitude of row yy-3, and its lane-edge neighbours
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     S.fx[P][i] = (float)gx[i];
     S.fy[P][i] = (float)gy[i];
     S.M[P][i] = __builtin_fmaf(S.fx[P][i], S.fx[P][i], S.fy[P][i] * S.fy[P][i]);
   }
+  S.ML[P] = from_left(S.M[P][3]);
+  S.MR[P] = from_right(S.M[P][0]);
 
   // ---- 6. suppression of row c = yy-4: up = Mpp, centre = M[Q], down = M[P]
   // (rows before the strip's first output are computed too and their stores
@@ -310,9 +320,9 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   const float* Mu = S.Mpp;
   const float* Mc = S.M[Q];
   const float* Md = S.M[P];
-  const float uL = from_left(Mu[3]), uR = from_right(Mu[0]);
-  const float cL = from_left(Mc[3]), cR = from_right(Mc[0]);
-  const float dL = from_left(Md[3]), dR = from_right(Md[0]);
+  const float uL = S.MppL, uR = S.MppR;
+  const float cL = S.ML[Q], cR = S.MR[Q];
+  const float dL = S.ML[P], dR = S.MR[P];
   float q[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -330,10 +340,15 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
     const float A = cH ? Cl : (cV ? Uc : (c45 ? Ul : Dl));
     const float B = cH ? Cr : (cV ? Dc : (c45 ? Dr : Ur));
     const float m = Mc[i];
-    // keep iff M(p) > M(p - d) and M(p) >= M(p + d), d = +e or -e
-    // (bitwise, so the decision stays in lane masks instead of branches)
-    const bool neg = (cV ? fy : fx) < 0.0f;
-    const bool keep = ((neg & (m > B) & (m >= A)) | (!neg & (m > A) & (m >= B))) & (m > 0.0f);
+    // keep iff M(p) > M(p - d) and M(p) >= M(p + d) and M(p) > 0, d = +e or
+    // -e by the sign of the gradient's component along e. Magnitudes are
+    // non-negative floats, so they order as their bit patterns, and "m > x"
+    // is "m >= the next float after x" = bits(x) + 1: one unsigned
+    // compare against a maximum decides the pixel.
+    const int sgn = (cV ? __float_as_int(fy) : __float_as_int(fx)) >> 31;  // -1 if d = -e, else 0
+    const uint32_t bA = __float_as_uint(A) + 1u + (uint32_t)sgn;           // strict unless d = -e
+    const uint32_t bB = __float_as_uint(B) - (uint32_t)sgn;                // strict if d = -e
+    const bool keep = __float_as_uint(m) >= max(max(bA, bB), 1u);
     const float v = St::kSquare ? m : __builtin_amdgcn_sqrtf(m) * kStoreScaleRoot;
     q[i] = keep ? v : 0.0f;
   }
@@ -344,10 +359,10 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
 #pragma unroll
     for (int i = 0; i < 4; ++i) bits[i] = __float_as_uint(q[i]);
     if constexpr (ALIGNED) {
-      __builtin_amdgcn_raw_buffer_store_b128(u32x4{bits[0], bits[1], bits[2], bits[3]}, mrow, C.store_off[0], 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(u32x4{bits[0], bits[1], bits[2], bits[3]}, mrow, C.store_off[0], 0, CPOL);
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) __builtin_amdgcn_raw_buffer_store_b32(bits[i], mrow, C.store_off[i], 0, 0);
+      for (int i = 0; i < 4; ++i) __builtin_amdgcn_raw_buffer_store_b32(bits[i], mrow, C.store_off[i], 0, CPOL);
     }
   } else {
     const uint32_t w0 = St::pack2(q[0], q[1]), w1 = St::pack2(q[2], q[3]);
@@ -356,11 +371,11 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
     bits[2] = w1 << 16;
     bits[3] = w1 & 0xFFFF0000u;
     if constexpr (ALIGNED) {
-      __builtin_amdgcn_raw_buffer_store_b64(u32x2{w0, w1}, mrow, C.store_off[0], 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b64(u32x2{w0, w1}, mrow, C.store_off[0], 0, CPOL);
     } else {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(bits[i] >> 16), mrow, C.store_off[i], 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(bits[i] >> 16), mrow, C.store_off[i], 0, CPOL);
     }
     if constexpr (PREC == IGSP_FP16) {
 #pragma unroll
@@ -373,19 +388,21 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
       atomicAdd(&hist[min(max((int)(bits[i] >> 16) - (int)Keys<PREC>::lo, 0), Keys<PREC>::bins - 1)], 1u);
 #pragma unroll
   for (int i = 0; i < 4; ++i) S.Mpp[i] = S.M[Q][i];
+  S.MppL = S.ML[Q];
+  S.MppR = S.MR[Q];
 }
 
-template <int PREC, bool NARROW, bool ALIGNED>
+template <int PREC, bool NARROW, bool ALIGNED, int CPOL>
 __device__ __forceinline__ void march(const StripCtx& C, uint32_t* hist) {
   StripState S = {};
   S.rows[0] = fetch_row<NARROW>(C, C.ys - kHalo);
   for (int t = 0; t < C.T; t += 2) {
-    strip_row<PREC, NARROW, ALIGNED, 0>(C, S, t, hist);
-    if (t + 1 < C.T) strip_row<PREC, NARROW, ALIGNED, 1>(C, S, t + 1, hist);
+    strip_row<PREC, NARROW, ALIGNED, 0, CPOL>(C, S, t, hist);
+    if (t + 1 < C.T) strip_row<PREC, NARROW, ALIGNED, 1, CPOL>(C, S, t + 1, hist);
   }
 }
 
-template <int PREC>
+template <int PREC, int CPOL = 0>
 __device__ __forceinline__ void wave_strip(const EdgeLaunch& L, const ViewDesc& vd, int x0, int ys, int ye,
                                            uint32_t* hist) {
   using St = Store<PREC>;
@@ -433,9 +450,9 @@ __device__ __forceinline__ void wave_strip(const EdgeLaunch& L, const ViewDesc& 
     C.store_off[i] = C.out_px[i] ? (cx0 + i) * ES : kDropOffset;
   }
   const bool aligned = (C.W & 3) == 0;  // then a lane's 4 outputs are all in or all out
-  if (narrow) march<PREC, true, false>(C, hist);
-  else if (aligned) march<PREC, false, true>(C, hist);
-  else march<PREC, false, false>(C, hist);
+  if (narrow) march<PREC, true, false, CPOL>(C, hist);
+  else if (aligned) march<PREC, false, true, CPOL>(C, hist);
+  else march<PREC, false, false, CPOL>(C, hist);
 }
 
 template <int PREC, int NW>
@@ -716,21 +733,27 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t v, uint32_t* tmp, uint
   return before + x - v;
 }
 
-// The end of one task: make this work-group's writes visible device-wide,
-// count the task off its phase, and tell every thread whether it was the
-// phase's last (then the count is restored for the next launch and the
-// other tasks' writes are acquired).
+// Data crosses work-groups of this launch only through device-coherent
+// accesses: the stored survivor values (kCpolAgent buffer stores and loads),
+// histograms (device-scope atomics, read back with coherent loads), the
+// selection state and the counters (relaxed agent-scope atomics). Ordering is
+// the hardware's: each wave waits for its own memory operations to complete
+// (s_waitcnt 0) before the work-group barrier that precedes the counter
+// update, and a reader issues its data loads only after the flag it waited
+// for has returned. So no release or acquire fence is needed, which on this
+// chip would write back or invalidate a whole XCD's L2 per task.
+__device__ __forceinline__ void drain() { __builtin_amdgcn_s_waitcnt(0); }
+
+// The end of one task: count it off its phase and tell every thread whether
+// it was the phase's last (then the count is restored for the next launch).
 template <int NW>
 __device__ __forceinline__ bool arrive(uint32_t* left, uint32_t restore, uint32_t* s_flag) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  drain();
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t old = __hip_atomic_fetch_add(left, 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool last = old == 1u;
-    if (last) {
-      st_agent(left, restore);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
+    if (last) st_agent(left, restore);
     *s_flag = last ? 1u : 0u;
   }
   __syncthreads();
@@ -739,7 +762,7 @@ __device__ __forceinline__ bool arrive(uint32_t* left, uint32_t restore, uint32_
 
 // Publish a view's selection step `level` (all threads call it).
 __device__ __forceinline__ void publish(uint32_t* ready, uint32_t level) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  drain();
   __syncthreads();
   if (threadIdx.x == 0) st_agent(ready, level);
 }
@@ -755,9 +778,42 @@ __device__ __forceinline__ void await(uint32_t* ready, uint32_t level, uint32_t*
         break;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
+}
+
+// Eight stored values at element p of a chunk whose first element sits at
+// `base`, through a device-coherent buffer load (p - p0 < 2^16, so the byte
+// offset fits the descriptor).
+template <int PREC>
+__device__ __forceinline__ void load8_coherent(__amdgpu_buffer_rsrc_t base, int off, float v[8]) {
+  using S = Store<PREC>;
+  if constexpr (PREC == IGSP_FP32) {
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(base, off * 4, 0, kCpolAgent);
+    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(base, off * 4 + 16, 0, kCpolAgent);
+    v[0] = __uint_as_float(a.x); v[1] = __uint_as_float(a.y); v[2] = __uint_as_float(a.z);
+    v[3] = __uint_as_float(a.w); v[4] = __uint_as_float(b.x); v[5] = __uint_as_float(b.y);
+    v[6] = __uint_as_float(b.z); v[7] = __uint_as_float(b.w);
+  } else {
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(base, off * 2, 0, kCpolAgent);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[2 * k] = S::widen((uint16_t)(w[k] & 0xFFFF));
+      v[2 * k + 1] = S::widen((uint16_t)(w[k] >> 16));
+    }
+  }
+}
+
+// Descriptor over the stored values of a flat chunk [p0, p1), rounded up to
+// whole groups of 8 (inside the view's padded region).
+template <int PREC>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const EdgeLaunch& L, const ViewDesc& vd,
+                                                             const FlatItem& it) {
+  using T = typename Store<PREC>::T;
+  const T* m = reinterpret_cast<const T*>(L.map) + vd.map_off + it.p0;
+  const int n8 = (int)((it.p1 - it.p0 + 7) & ~int64_t(7));
+  return buffer_rsrc(m, n8 * (int)sizeof(T));
 }
 
 // First selection step of view v from its global histogram (then cleared).
@@ -842,14 +898,15 @@ __device__ void refine_chunk(const EdgeLaunch& L, const FlatItem& it, const MedS
     const ViewDesc vd = L.views[it.view];
     const int dshift = st.shift - digit_bits;
     const uint32_t dmask = (1u << digit_bits) - 1u;
-    const typename Store<PREC>::T* m = reinterpret_cast<const typename Store<PREC>::T*>(L.map) + vd.map_off;
-    for (int64_t p = it.p0 + 8 * threadIdx.x; p < it.p1; p += 8 * NT) {
+    const __amdgpu_buffer_rsrc_t mr = chunk_rsrc<PREC>(L, vd, it);
+    const int n = (int)(it.p1 - it.p0);
+    for (int p = 8 * threadIdx.x; p < n; p += 8 * NT) {
       float v[8];
-      load8<PREC>(m, p, v);
+      load8_coherent<PREC>(mr, p, v);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const uint32_t bits = __float_as_uint(v[i]);
-        if (p + i < it.p1 && v[i] > 0.0f && (bits >> st.shift) == st.prefix)
+        if (p + i < n && v[i] > 0.0f && (bits >> st.shift) == st.prefix)
           atomicAdd(&hs[(bits >> dshift) & dmask], 1u);
       }
     }
@@ -867,27 +924,27 @@ __device__ void norm_chunk(const EdgeLaunch& L, const FlatItem& it, float med) {
   constexpr int NT = NW * 64, STEP = 8 * NT;
   const ViewDesc vd = L.views[it.view];
   const float inv = med > 0.0f ? 1.0f / med : 0.0f;
-  const typename Store<PREC>::T* m = reinterpret_cast<const typename Store<PREC>::T*>(L.map) + vd.map_off;
-  gptr<float> out = as_global(L.out + vd.out_off);
-  const bool aligned = (vd.out_off & 3) == 0;
-  for (int64_t p0 = it.p0 + 8 * threadIdx.x; p0 < it.p1; p0 += kNormUnroll * STEP) {
+  const __amdgpu_buffer_rsrc_t mr = chunk_rsrc<PREC>(L, vd, it);
+  gptr<float> out = as_global(L.out + vd.out_off + it.p0);
+  const bool aligned = ((vd.out_off + it.p0) & 3) == 0;
+  const int n = (int)(it.p1 - it.p0);
+  for (int p0 = 8 * threadIdx.x; p0 < n; p0 += kNormUnroll * STEP) {
     float v[kNormUnroll][8];
 #pragma unroll
-    for (int u = 0; u < kNormUnroll; ++u)
-      if (p0 + u * STEP < it.p1) load8<PREC>(m, p0 + u * STEP, v[u]);
+    for (int u = 0; u < kNormUnroll; ++u) load8_coherent<PREC>(mr, p0 + u * STEP, v[u]);  // past the end: 0
 #pragma unroll
     for (int u = 0; u < kNormUnroll; ++u) {
-      const int64_t p = p0 + u * STEP;
-      if (p >= it.p1) break;
+      const int p = p0 + u * STEP;
+      if (p >= n) break;
       float e[8];
       normalise8<PREC>(v[u], med, inv, e);
-      if (aligned && p + 8 <= it.p1) {
+      if (aligned && p + 8 <= n) {
         *(gptr<f32x4>)(out + p) = f32x4{e[0], e[1], e[2], e[3]};
         *(gptr<f32x4>)(out + p + 4) = f32x4{e[4], e[5], e[6], e[7]};
       } else {
 #pragma unroll
         for (int i = 0; i < 8; ++i)
-          if (p + i < it.p1) out[p + i] = e[i];
+          if (p + i < n) out[p + i] = e[i];
       }
     }
   }
@@ -923,7 +980,7 @@ edge_persistent_kernel(EdgeLaunch L, PersistLaunch P) {
       const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
       const int ys = it.y0 + w * L.seg_rows;
       const int ye = min(ys + L.seg_rows, it.y0 + it.rows);
-      if (ys < ye) wave_strip<PREC>(L, vd, it.x0, ys, ye, lds);
+      if (ys < ye) wave_strip<PREC, kCpolAgent>(L, vd, it.x0, ys, ye, lds);
       __syncthreads();
       uint32_t* gh = L.hist + (int64_t)v * kBinsMax;
       for (int i = threadIdx.x; i < NB; i += NT) {

@@ -129,12 +129,17 @@ int ilog2(int64_t v) {
   return r;
 }
 
+// Architecture name of the current device ("gfx950"), cached per device.
 std::string device_arch() {
+  static std::map<int, std::string> cache;
   int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
   hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
   std::string a = prop.gcnArchName;
-  return a.substr(0, a.find(':'));
+  return cache[dev] = a.substr(0, a.find(':'));
 }
 
 TuneKey tune_key(const igsp_view* views, int32_t n, int precision, int batched) {
@@ -150,10 +155,7 @@ TuneKey tune_key(const igsp_view* views, int32_t n, int precision, int batched) 
 // The cache file: one JSON object per line,
 // {"arch":"gfx950","precision":2,"batched":1,"log2_px":29,"log2_w":10,"seg_rows":64,"wg_waves":4,
 //  "form":3,"ms":1.3}
-void load_tune_cache() {
-  if (g_tune_loaded) return;
-  g_tune_loaded = true;
-  const char* path = std::getenv("IGSP_TUNE_CACHE");
+void read_tune_file(const char* path) {
   if (!path || !*path) return;
   std::FILE* f = std::fopen(path, "r");
   if (!f) return;
@@ -165,12 +167,26 @@ void load_tune_cache() {
                     " {\"arch\":\"%63[^\"]\",\"precision\":%d,\"batched\":%d,\"log2_px\":%d,\"log2_w\":%d,"
                     "\"seg_rows\":%d,\"wg_waves\":%d,\"form\":%d,\"ms\":%lf",
                     arch, &k.precision, &k.batched, &k.log2_px, &k.log2_w, &v.seg_rows, &v.wg_waves, &v.form,
-                    &v.ms) == 9) {
-      k.arch = arch;
-      g_tuned[k] = v;
-    }
+                    &v.ms) != 9)
+      continue;
+    const bool ok = k.precision >= IGSP_FP32 && k.precision <= IGSP_BF16 && k.batched >= IGSP_PLAIN &&
+                    k.batched <= IGSP_BATCHED_PERSISTENT && v.seg_rows >= 8 && v.seg_rows <= 4096 &&
+                    (v.wg_waves == 1 || v.wg_waves == 2 || v.wg_waves == 4 || v.wg_waves == 8) &&
+                    v.form >= IGSP_PLAIN && v.form <= IGSP_BATCHED_PERSISTENT && v.form != IGSP_BATCHED;
+    if (!ok) continue;  // malformed entries are ignored
+    k.arch = arch;
+    g_tuned[k] = v;
   }
   std::fclose(f);
+}
+
+// Tuned entries: first the shipped table (IGSP_TUNE_DEFAULTS, read only), then
+// the caller's cache (IGSP_TUNE_CACHE), whose entries win.
+void load_tune_cache() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  read_tune_file(std::getenv("IGSP_TUNE_DEFAULTS"));
+  read_tune_file(std::getenv("IGSP_TUNE_CACHE"));
 }
 
 void save_tune_cache() {
@@ -495,6 +511,28 @@ extern "C" igsp_status long_axis_split(const igsp_gaussians* g, const uint8_t* m
   st = get_las_plan(g->capacity, &plan);
   if (st != IGSP_OK) return st;
   return enqueue_las(plan.get(), g, mask, out, params, static_cast<hipStream_t>(stream));
+}
+
+extern "C" igsp_status igsp_edge_resolve(const igsp_view* views, int32_t n_views, igsp_edge_opts* opts) {
+  if (!opts || (n_views > 0 && !views)) return IGSP_ERR_NULL;
+  if (n_views < 0) return IGSP_ERR_DIMS;
+  if (opts->precision < IGSP_FP32 || opts->precision > IGSP_BF16) return IGSP_ERR_PARAM;
+  if (opts->batched < IGSP_PLAIN || opts->batched > IGSP_BATCHED_PERSISTENT) return IGSP_ERR_PARAM;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int form = resolve_form(views, n_views, opts);
+  int seg = default_seg_rows(), wgw = default_wg_waves();
+  if (opts->seg_rows == 0 && opts->wg_waves == 0) {
+    load_tune_cache();
+    auto it = g_tuned.find(tune_key(views, n_views, opts->precision, opts->batched));
+    if (it != g_tuned.end()) {
+      seg = it->second.seg_rows;
+      wgw = it->second.wg_waves;
+    }
+  }
+  opts->batched = form;
+  if (opts->seg_rows == 0) opts->seg_rows = seg;
+  if (opts->wg_waves == 0) opts->wg_waves = wgw;
+  return IGSP_OK;
 }
 
 extern "C" igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view* views, int32_t n_views,

@@ -132,3 +132,31 @@ def test_null_stage_event_rejected():
     ev = (ctypes.c_void_p * 4)(1, 2, None, 4)
     o = B.EdgeOpts(0, 1, 0, 0, None, None, ctypes.cast(ev, ctypes.c_void_p))
     assert edge(GOOD, opts=o) == -1
+
+
+def test_tuning_table_lookup_and_override(tmp_path):
+    """The shipped table and the caller's cache are read once per process
+    (a fresh interpreter here): entries of the view batch's size class pick
+    the form and tile, the cache wins over the table, and malformed lines or
+    out-of-range values are ignored."""
+    import subprocess
+    import sys
+
+    # 1000 x 800: 800000 px -> log2 19; mean width 1000 -> log2 9; no GPU -> arch "unknown"
+    row = ('{{"arch":"unknown","precision":2,"batched":1,"log2_px":19,"log2_w":9,'
+           '"seg_rows":{s},"wg_waves":{w},"form":{f},"ms":1.0}}')
+    table = tmp_path / "table.jsonl"
+    table.write_text("not json\n" + row.format(s=96, w=2, f=3) + "\n"
+                     + row.format(s=96, w=3, f=3).replace('"precision":2', '"precision":1') + "\n")
+    cache = tmp_path / "cache.jsonl"
+    code = ("import paper_2603_08661_amd as g; v=([1000],[800],[0],[0]);"
+            "print(g.edge_resolve(v,'bf16'), g.edge_resolve(v,'fp16'), g.edge_resolve(v,'bf16',seg_rows=32),"
+            " g.edge_resolve(v,'bf16','staged'))")
+    env = dict(os.environ, IGSP_TUNE_DEFAULTS=str(table), IGSP_TUNE_CACHE=str(cache))
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         check=True).stdout.strip()
+    assert out == ("('persistent', 96, 2) ('staged', 64, 4) ('persistent', 32, 4) ('staged', 64, 4)"), out
+    cache.write_text(row.format(s=48, w=8, f=2) + "\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         check=True).stdout.strip()
+    assert out.startswith("('staged', 48, 8)"), out
