@@ -83,7 +83,11 @@ def summarise_profile(d: str, copy_bytes: int):
 
     res = json.loads(open(os.path.join(d, "bench.json")).read().strip().splitlines()[-1])
     kernel = res["roofline"]["kernel"]
-    sym = {"edge_fused": "edge_fused_kernel", "edge_persistent": "edge_persistent_kernel"}[kernel]
+    # the instantiation the timed form runs: <storage precision, wavefronts per work-group>
+    prec_code = {"fp32": 0, "fp16": 1, "bf16": 2}[res["config"]["intermediate"]]
+    nw = int(res["config"]["tile"].split("x")[1])
+    sym = {"edge_fused": "edge_fused_kernel", "edge_persistent": "edge_persistent_kernel"}[kernel] + \
+        f"<{prec_code}, {nw}>"
     stats = _csv_rows(os.path.join(d, "trace", "**", "*kernel_stats.csv"))
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     wl = res["config"]["workload"]
