@@ -141,7 +141,8 @@ int persistent_blocks_per_cu(int precision, int wg_waves);
 
 constexpr int kLasThreads = 256;
 constexpr int kLasRounds = 8;
-constexpr int kLasRows = kLasThreads * kLasRounds;  // rows per block
+constexpr int kLasRows = kLasThreads * kLasRounds;  // rows per tile (8 per thread)
+constexpr int kLasGrid = 1024;                      // work-groups of the count and split kernels
 
 struct LasScalars {
   int64_t n_live;    // N read before the split
