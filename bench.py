@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edge-map megapixels/s + Gaussians split/s, batched-FP16 vs plain-FP32, % HBM peak"
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes per cycle x clock (non-packed)
 COPY_CAL_BYTES = 1 << 30
 STORE_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
 
@@ -118,6 +119,8 @@ def summarise_profile(d: str, copy_bytes: int):
                          "FETCH_SIZE")
     cw, _ = _counter_kib(_csv_rows(os.path.join(d, "copy_write", "**", "*counter_collection.csv")), "copy",
                          "WRITE_SIZE")
+    valu, nv = _counter_kib(_csv_rows(os.path.join(d, "valu", "**", "*counter_collection.csv")), sym,
+                            "SQ_INSTS_VALU")
     f_fetch = copy_bytes / (cf * 1024) if cf else None
     f_write = copy_bytes / (cw * 1024) if cw else None
     traffic = (fetch * 1024 * f_fetch + write * 1024 * f_write) if None not in (fetch, write, f_fetch, f_write) \
@@ -136,6 +139,7 @@ def summarise_profile(d: str, copy_bytes: int):
          f"fetch_scale: {f_fetch}", f"write_scale: {f_write}",
          f"traffic_bytes_per_launch: {traffic}",
          f"algorithmic_bytes_per_launch: {res['roofline']['bytes_per_launch']}",
+         f"valu_insts_per_launch: {valu} ({nv} dispatches; SQ_INSTS_VALU, wave instructions)",
          "",
          "  Commands (repo root, TMPDIR=/tmp), each pass in its own run:",
          f"    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o p -- {pmc_cmd}",
@@ -144,6 +148,8 @@ def summarise_profile(d: str, copy_bytes: int):
          f"python3 bench.py --copy-calibration {copy_bytes}",
          f"    timeout -s KILL 60 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/copy_write -o p -- "
          f"python3 bench.py --copy-calibration {copy_bytes}",
+         f"    timeout -s KILL 120 rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES --output-format csv -d <dir>/valu -o p -- "
+         f"{pmc_cmd}",
          "    python3 bench.py --summarise-profile <dir>",
          "  FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by copy_bytes / (1024 x what the same",
          "  counter reads for the plain copy of copy_bytes bytes). traffic = scaled fetch + scaled write."]
@@ -152,10 +158,10 @@ def summarise_profile(d: str, copy_bytes: int):
                       avg[0] / 1e6 if avg else None, "live_ms": res["stage_ms"]["fused"]}))
 
 
-def traffic_from_profile(kernel: str, prec: str, workload: str, seg_rows: int, wg_waves: int):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when that summary was taken on another kernel source,
-    workload, storage precision or tile shape."""
+def profile_facts(kernel: str, prec: str, workload: str, seg_rows: int, wg_waves: int) -> dict:
+    """Counter facts (HBM bytes, VALU instructions per launch) of the dominant
+    kernel from the committed summary, or {} when that summary was taken on
+    another kernel source, workload, storage precision or tile shape."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic.txt")
@@ -169,10 +175,16 @@ def traffic_from_profile(kernel: str, prec: str, workload: str, seg_rows: int, w
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
         if (kv.get("kernel_source_sha256") != digest or kv.get("precision") != prec
                 or kv.get("workload") != workload or kv.get("tile") != f"{seg_rows}x{wg_waves}"):
-            return None
-        return int(float(kv["traffic_bytes_per_launch"]))
-    except (OSError, KeyError, ValueError, TypeError):
-        return None
+            return {}
+    except OSError:
+        return {}
+    out = {}
+    for key in ("traffic_bytes_per_launch", "valu_insts_per_launch"):
+        try:
+            out[key] = int(float(kv[key].split()[0]))
+        except (KeyError, ValueError, IndexError):
+            pass
+    return out
 
 
 def main():
@@ -323,6 +335,17 @@ def main():
     achieved = fused_bytes / (stage_ms["fused"] * 1e-3) / 1e9
     log(f"stages: {stage_ms}, las {las_ms}")
 
+    # ---- practical ceiling of a read+write stream: a plain device copy
+    cbytes = 1 << 30
+    csrc = torch.empty(cbytes, dtype=torch.uint8, device=dev)
+    cdst = torch.empty_like(csrc)
+    def copy_once():
+        with torch.cuda.stream(stream):
+            cdst.copy_(csrc)
+    cms, _ = timed(copy_once, 2, 10)
+    copy_gbps = 2 * cbytes / (cms * 1e-3) / 1e9
+    del csrc, cdst
+
     # ---- plain per-view FP32 form of the same step
     plain = None
     if not args.no_plain:
@@ -355,9 +378,19 @@ def main():
         oracle.edge_batch(sub.rgb, sub.widths, sub.heights, sub.in_offset, sub.out_offset, sub.out_floats,
                           threads=threads)
         te = time.perf_counter() - t1
+        # the same oracle on one core, on a shorter prefix of the views
+        per_view_1core = te * threads / max(nsamp, 1)
+        n1 = max(1, min(nsamp, int(round(args.cpu_seconds / 2 / max(per_view_1core, 1e-3)))))
+        sub1 = synth.pack_views([vb.view(v) for v in range(n1)])
+        t1 = time.perf_counter()
+        oracle.edge_batch(sub1.rgb, sub1.widths, sub1.heights, sub1.in_offset, sub1.out_offset, sub1.out_floats,
+                          threads=1)
+        t1c = time.perf_counter() - t1
         cpu = {"value": round(sub.pixels / 1e6 / te, 3), "unit": "MPx/s", "cores": threads, "kind": "oracle",
+               "value_1core": round(sub1.pixels / 1e6 / t1c, 3),
                "sample": f"edge maps of the first {nsamp} views ({sub.pixels / 1e6:.1f} MPx) of the same "
-                         f"workload, views spread over {threads} threads, {te:.1f}s"}
+                         f"workload, views spread over {threads} threads, {te:.1f}s; on 1 core the first "
+                         f"{n1} views ({sub1.pixels / 1e6:.1f} MPx), {t1c:.1f}s"}
         if has_las:
             n_l = min(N0, 1_000_000)
             k_l = int(mk[:n_l].sum())
@@ -373,6 +406,19 @@ def main():
             cpu["sample"] += f"; split of the first {n_l} Gaussians ({r['K']} selected) on 1 thread, {tl:.2f}s"
         log(f"cpu baseline: {cpu}")
 
+    prof = profile_facts(kernel, prec, w.name, seg, wgw)
+    traffic = prof.get("traffic_bytes_per_launch")
+    roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "algorithmic_bytes_per_px": per_px, "bytes_per_launch": int(fused_bytes)}
+    if traffic:
+        tg = traffic / (stage_ms["fused"] * 1e-3) / 1e9
+        roof["traffic_GBps"] = round(tg, 1)
+        roof["traffic_frac"] = round(tg / HBM_PEAK_GBS, 4)
+    if prof.get("valu_insts_per_launch"):
+        lane_ops = prof["valu_insts_per_launch"] * 64
+        roof["valu_lane_ops_per_px"] = round(lane_ops / vb.pixels, 2)
+        roof["valu_frac"] = round(lane_ops / (stage_ms["fused"] * 1e-3) / VALU_PEAK_LANE_OPS, 4)
     res = {
         "metric": METRIC,
         "value": round(mpx / (ms * 1e-3), 1),
@@ -392,11 +438,8 @@ def main():
                    "arithmetic": "int32 exact through Sobel, fp32 magnitude/suppression/median/LAS"},
         "wall_ms_per_step": round(wall, 4),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profile(kernel, prec, w.name, seg, wgw),
-                     "algorithmic_bytes_per_px": per_px,
-                     "bytes_per_launch": int(fused_bytes)},
+        "roofline": roof,
+        "copy_ceiling_GBps": round(copy_gbps, 1),
         "edge_pipeline": {"ms": round(stage_ms["edge"], 4),
                           "mpx_per_s": round(mpx / (stage_ms["edge"] * 1e-3), 1),
                           "algorithmic_GBps": round(vb.pixels * 7 / (stage_ms["edge"] * 1e-3) / 1e9, 1),

@@ -197,17 +197,16 @@ __device__ __forceinline__ void gray4(uint32_t d0, uint32_t d1, uint32_t d2, int
 // ------------------------------------------------------------- stage 1
 
 // Loop-carried state of one wavefront's march down its strip. Depth-one
-// windows are kept twice and addressed by the parity of the row, so after
-// unrolling the loop by two every value stays in its register (no copies).
+// windows are kept twice and addressed by the parity of the row, the
+// magnitude rows three times and addressed by the row modulo 3, so after
+// unrolling the loop by six every value stays in its register (no copies).
 struct StripState {
   Lane12 rows[2];                  // raw bytes: this row / next row
   int h[2][4], s1[2][4], s2[2][4], s3[2][4];   // vertical (1 1)^4 cascade
   int sx[2][4], u1[2][4];          // gx cascade
-  int bprev[2][4];                 // blurred rows r-1 (other parity) and r-2 (same parity)
-  float M[2][4];                   // squared magnitude, last two rows
-  float ML[2], MR[2];              // and the lanes' outer neighbours of each
-  float Mpp[4];                    // the row before them
-  float MppL, MppR;
+  int b[2][4];                     // blurred rows r-1 (other parity) and r-2 (same parity)
+  float M[3][4];                   // squared magnitude of the last three rows
+  float ML[3], MR[3];              // and the lanes' outer neighbours of each
   float fx[2][4], fy[2][4];        // gradient of the last two rows (exact in float for |g| < 2^24,
                                    // else rounded; only its orientation is read back)
 };
@@ -244,10 +243,13 @@ __device__ __forceinline__ Lane12 fetch_row(const StripCtx& C, int yy) {
   else return load_lane(row, C.win_off);
 }
 
-template <int PREC, bool NARROW, bool ALIGNED, int P, int CPOL>
+template <int PREC, bool NARROW, bool ALIGNED, int P, int MS, int CPOL>
 __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int t, uint32_t* hist) {
   using St = Store<PREC>;
-  constexpr int Q = P ^ 1;  // previous row's slot
+  constexpr int Q = P ^ 1;             // previous row's parity slot
+  constexpr int MD = MS;               // magnitude slots: new (down) row,
+  constexpr int MC = (MS + 2) % 3;     // the row before it (centre),
+  constexpr int MU = (MS + 1) % 3;     // and the one before that (up)
   constexpr int ES = sizeof(typename St::T);
   // ---- prefetch the next row (the last step re-reads a row: one load per
   //      step keeps the wait for this row from draining the prefetch)
@@ -294,8 +296,8 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   for (int i = 0; i < 4; ++i) {
     S.u1[P][i] = S.sx[P][i] + S.sx[Q][i];
     gx[i] = S.u1[P][i] + S.u1[Q][i];
-    sy[i] = b[i] - S.bprev[P][i];     // the same parity slot still holds b(r-2)
-    S.bprev[P][i] = b[i];
+    sy[i] = b[i] - S.b[P][i];          // the same parity slot still holds b(r-2)
+    S.b[P][i] = b[i];
   }
   const int syL = from_left(sy[3]), syR = from_right(sy[0]);
   const int gy[4] = {syL + 2 * sy[0] + sy[1], sy[0] + 2 * sy[1] + sy[2], sy[1] + 2 * sy[2] + sy[3],
@@ -306,29 +308,26 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   for (int i = 0; i < 4; ++i) {
     S.fx[P][i] = (float)gx[i];
     S.fy[P][i] = (float)gy[i];
-    S.M[P][i] = __builtin_fmaf(S.fx[P][i], S.fx[P][i], S.fy[P][i] * S.fy[P][i]);
+    S.M[MD][i] = __builtin_fmaf(S.fx[P][i], S.fx[P][i], S.fy[P][i] * S.fy[P][i]);
   }
-  S.ML[P] = from_left(S.M[P][3]);
-  S.MR[P] = from_right(S.M[P][0]);
+  S.ML[MD] = from_left(S.M[MD][3]);
+  S.MR[MD] = from_right(S.M[MD][0]);
 
-  // ---- 6. suppression of row c = yy-4: up = Mpp, centre = M[Q], down = M[P]
+  // ---- 6. suppression of row c = yy-4: up = M[MU], centre = M[MC], down = M[MD]
   // (rows before the strip's first output are computed too and their stores
   // dropped, so the loop body has no branch around memory operations)
   const float kTan = 0.41421356237309503f;  // tan(22.5 deg) = sqrt(2) - 1
   const int c = C.ys - 2 * kHalo + t;
-  const bool row_out = t >= 2 * kHalo;
-  const float* Mu = S.Mpp;
-  const float* Mc = S.M[Q];
-  const float* Md = S.M[P];
-  const float uL = S.MppL, uR = S.MppR;
-  const float cL = S.ML[Q], cR = S.MR[Q];
-  const float dL = S.ML[P], dR = S.MR[P];
+  const bool row_out = t >= 2 * kHalo && t < C.T;
+  const float* Mu = S.M[MU];
+  const float* Mc = S.M[MC];
+  const float* Md = S.M[MD];
   float q[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const float Ul = i > 0 ? Mu[i - 1] : uL, Uc = Mu[i], Ur = i < 3 ? Mu[i + 1] : uR;
-    const float Cl = i > 0 ? Mc[i - 1] : cL, Cr = i < 3 ? Mc[i + 1] : cR;
-    const float Dl = i > 0 ? Md[i - 1] : dL, Dc = Md[i], Dr = i < 3 ? Md[i + 1] : dR;
+    const float Ul = i > 0 ? Mu[i - 1] : S.ML[MU], Uc = Mu[i], Ur = i < 3 ? Mu[i + 1] : S.MR[MU];
+    const float Cl = i > 0 ? Mc[i - 1] : S.ML[MC], Cr = i < 3 ? Mc[i + 1] : S.MR[MC];
+    const float Dl = i > 0 ? Md[i - 1] : S.ML[MD], Dc = Md[i], Dr = i < 3 ? Md[i + 1] : S.MR[MD];
     // orientation bin: within 22.5 degrees of the x axis, of the y axis, or
     // diagonal (gx, gy of equal sign: (1,1), else (1,-1)); tan 22.5 = sqrt 2 - 1
     const float fx = S.fx[Q][i], fy = S.fy[Q][i];
@@ -342,9 +341,8 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
     const float m = Mc[i];
     // keep iff M(p) > M(p - d) and M(p) >= M(p + d) and M(p) > 0, d = +e or
     // -e by the sign of the gradient's component along e. Magnitudes are
-    // non-negative floats, so they order as their bit patterns, and "m > x"
-    // is "m >= the next float after x" = bits(x) + 1: one unsigned
-    // compare against a maximum decides the pixel.
+    // non-negative floats, so they order as their bit patterns and "m > x"
+    // is "m >= next float after x" = bits(x) + 1: one unsigned max-compare.
     const int sgn = (cV ? __float_as_int(fy) : __float_as_int(fx)) >> 31;  // -1 if d = -e, else 0
     const uint32_t bA = __float_as_uint(A) + 1u + (uint32_t)sgn;           // strict unless d = -e
     const uint32_t bB = __float_as_uint(B) - (uint32_t)sgn;                // strict if d = -e
@@ -386,19 +384,22 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   for (int i = 0; i < 4; ++i)
     if (row_out && bits[i] != 0u && C.out_px[i])
       atomicAdd(&hist[min(max((int)(bits[i] >> 16) - (int)Keys<PREC>::lo, 0), Keys<PREC>::bins - 1)], 1u);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) S.Mpp[i] = S.M[Q][i];
-  S.MppL = S.ML[Q];
-  S.MppR = S.MR[Q];
 }
 
 template <int PREC, bool NARROW, bool ALIGNED, int CPOL>
 __device__ __forceinline__ void march(const StripCtx& C, uint32_t* hist) {
   StripState S = {};
   S.rows[0] = fetch_row<NARROW>(C, C.ys - kHalo);
-  for (int t = 0; t < C.T; t += 2) {
-    strip_row<PREC, NARROW, ALIGNED, 0, CPOL>(C, S, t, hist);
-    if (t + 1 < C.T) strip_row<PREC, NARROW, ALIGNED, 1, CPOL>(C, S, t + 1, hist);
+  // six rows per iteration (parity slot t % 2, magnitude slot t % 3), with no
+  // exit inside the body: rows past the strip's last one (up to five) are
+  // computed and neither stored nor counted
+  for (int t = 0; t < C.T; t += 6) {
+    strip_row<PREC, NARROW, ALIGNED, 0, 0, CPOL>(C, S, t, hist);
+    strip_row<PREC, NARROW, ALIGNED, 1, 1, CPOL>(C, S, t + 1, hist);
+    strip_row<PREC, NARROW, ALIGNED, 0, 2, CPOL>(C, S, t + 2, hist);
+    strip_row<PREC, NARROW, ALIGNED, 1, 0, CPOL>(C, S, t + 3, hist);
+    strip_row<PREC, NARROW, ALIGNED, 0, 1, CPOL>(C, S, t + 4, hist);
+    strip_row<PREC, NARROW, ALIGNED, 1, 2, CPOL>(C, S, t + 5, hist);
   }
 }
 
@@ -626,40 +627,75 @@ __device__ __forceinline__ void normalise8(const float v[8], float med, float in
   }
 }
 
-// Element-wise normalisation of one flat chunk of a view. Each thread keeps
-// kNormUnroll groups of 8 stored values in flight before converting and
-// storing them, so a wave has several 1 KB loads outstanding.
-constexpr int kNormUnroll = 2;
+// Element-wise normalisation of one flat chunk of a view. Buffer descriptors
+// over the chunk take the bounds checks: each thread keeps kNormUnroll groups
+// of 8 stored values in flight, and groups past the chunk read 0 and store
+// nothing. The chunk's last, partial group (a view's pixel count need not be
+// a multiple of 8) is written again element by element at the end.
+constexpr int kNormUnroll = 4;
+
+template <int PREC>
+__device__ __forceinline__ void load8_buf(__amdgpu_buffer_rsrc_t base, int p, float v[8]) {
+  using S = Store<PREC>;
+  if constexpr (PREC == IGSP_FP32) {
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(base, p * 4, 0, 0);
+    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(base, p * 4 + 16, 0, 0);
+    v[0] = __uint_as_float(a.x); v[1] = __uint_as_float(a.y); v[2] = __uint_as_float(a.z);
+    v[3] = __uint_as_float(a.w); v[4] = __uint_as_float(b.x); v[5] = __uint_as_float(b.y);
+    v[6] = __uint_as_float(b.z); v[7] = __uint_as_float(b.w);
+  } else {
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(base, p * 2, 0, 0);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[2 * k] = S::widen((uint16_t)(w[k] & 0xFFFF));
+      v[2 * k + 1] = S::widen((uint16_t)(w[k] >> 16));
+    }
+  }
+}
 
 template <int PREC>
 __global__ __launch_bounds__(256) void normalise_kernel(EdgeLaunch L, int flat0) {
+  using T = typename Store<PREC>::T;
+  constexpr int STEP = 8 * 256;
   const FlatItem it = L.flat[flat0 + blockIdx.x];
   const ViewDesc vd = L.views[it.view];
   const float med = L.state[it.view].med;
   const float inv = med > 0.0f ? 1.0f / med : 0.0f;
-  const typename Store<PREC>::T* m = reinterpret_cast<const typename Store<PREC>::T*>(L.map) + vd.map_off;
-  gptr<float> out = as_global(L.out + vd.out_off);
-  const bool aligned = (vd.out_off & 3) == 0;
-  constexpr int STEP = 8 * 256;
-  for (int64_t p0 = it.p0 + 8 * threadIdx.x; p0 < it.p1; p0 += kNormUnroll * STEP) {
+  const int n = (int)(it.p1 - it.p0);
+  const int n8 = (n + 7) & ~7;  // the view's map region is padded to 64 elements
+  const __amdgpu_buffer_rsrc_t in =
+      buffer_rsrc(reinterpret_cast<const T*>(L.map) + vd.map_off + it.p0, n8 * (int)sizeof(T));
+  float* outp = L.out + vd.out_off + it.p0;
+  const __amdgpu_buffer_rsrc_t out = buffer_rsrc(outp, n * 4);
+  for (int p0 = 8 * threadIdx.x; p0 < n; p0 += kNormUnroll * STEP) {
     float v[kNormUnroll][8];
 #pragma unroll
-    for (int u = 0; u < kNormUnroll; ++u)
-      if (p0 + u * STEP < it.p1) load8<PREC>(m, p0 + u * STEP, v[u]);
+    for (int u = 0; u < kNormUnroll; ++u) load8_buf<PREC>(in, p0 + u * STEP, v[u]);
 #pragma unroll
     for (int u = 0; u < kNormUnroll; ++u) {
-      const int64_t p = p0 + u * STEP;
-      if (p >= it.p1) break;
       float e[8];
       normalise8<PREC>(v[u], med, inv, e);
-      if (aligned && p + 8 <= it.p1) {
-        *(gptr<f32x4>)(out + p) = f32x4{e[0], e[1], e[2], e[3]};
-        *(gptr<f32x4>)(out + p + 4) = f32x4{e[4], e[5], e[6], e[7]};
-      } else {
+      const int p = p0 + u * STEP;
+      __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(e[0]), __float_as_uint(e[1]),
+                                                   __float_as_uint(e[2]), __float_as_uint(e[3])},
+                                             out, p * 4, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(e[4]), __float_as_uint(e[5]),
+                                                   __float_as_uint(e[6]), __float_as_uint(e[7])},
+                                             out, p * 4 + 16, 0, 0);
+    }
+  }
+  if (n & 7) {  // the partial last group, element by element
+    const int p = n & ~7;
+    if (threadIdx.x < n - p) {
+      float v[8], e[8];
+      load8_buf<PREC>(in, p, v);
+      normalise8<PREC>(v, med, inv, e);
+      const int k = threadIdx.x;
+      float ek = e[0];
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (p + i < it.p1) out[p + i] = e[i];
-      }
+      for (int i = 1; i < 8; ++i) ek = k == i ? e[i] : ek;
+      as_global(outp)[p + k] = ek;
     }
   }
 }
