@@ -33,8 +33,14 @@
 
 #include "igsp_internal.h"
 
+// Waves per SIMD the register allocation is held to (128 VGPRs at 4; the
+// stencil needs about 110). Five waves fit its hot loop in 96 VGPRs but gain
+// nothing measurable: the loop is bound by vector-ALU issue, not latency.
 #ifndef IGSP_FUSED_WAVES_PER_EU
 #define IGSP_FUSED_WAVES_PER_EU 4
+#endif
+#ifndef IGSP_PERSIST_WAVES_PER_EU
+#define IGSP_PERSIST_WAVES_PER_EU 4
 #endif
 
 namespace igsp {
@@ -202,9 +208,11 @@ __device__ __forceinline__ void gray4(uint32_t d0, uint32_t d1, uint32_t d2, int
 // unrolling the loop by six every value stays in its register (no copies).
 struct StripState {
   Lane12 rows[2];                  // raw bytes: this row / next row
-  int h[2][4], s1[2][4], s2[2][4], s3[2][4];   // vertical (1 1)^4 cascade
-  int sx[2][4], u1[2][4];          // gx cascade
-  int b[2][4];                     // blurred rows r-1 (other parity) and r-2 (same parity)
+  // rows r-1 (other parity slot) and r-2 (same parity slot) of:
+  int h[2][4];                     // the horizontal blur
+  int tv[2][4];                    // its first vertical (1 2 1) pass
+  int sx[2][4];                    // the horizontal difference of the blur
+  int b[2][4];                     // the blur
   float M[3][4];                   // squared magnitude of the last three rows
   float ML[3], MR[3];              // and the lanes' outer neighbours of each
   float fx[2][4], fy[2][4];        // gradient of the last two rows (exact in float for |g| < 2^24,
@@ -273,29 +281,25 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   h[2] = mad24(g[2], 6, (g[0] + gR0) + 4 * (g[1] + g[3]));
   h[3] = mad24(g[3], 6, (g[1] + gR1) + 4 * (g[2] + gR0));
 
-  // ---- 3. vertical taps as four (1 1) sums: b = blur of row yy-2
+  // ---- 3. vertical taps (1 4 6 4 1) = (1 2 1) twice: b = blur of row yy-2
   int b[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
+    const int tv = S.h[P][i] + 2 * S.h[Q][i] + h[i];       // centred on row yy-1
     S.h[P][i] = h[i];
-    S.s1[P][i] = h[i] + S.h[Q][i];
-    S.s2[P][i] = S.s1[P][i] + S.s1[Q][i];
-    S.s3[P][i] = S.s2[P][i] + S.s2[Q][i];
-    b[i] = S.s3[P][i] + S.s3[Q][i];
+    b[i] = S.tv[P][i] + 2 * S.tv[Q][i] + tv;              // centred on row yy-2
+    S.tv[P][i] = tv;
   }
 
   // ---- 4. Sobel of row yy-3: gx = (1 2 1)^T on the horizontal difference,
   //      gy = (1 2 1) along x on the vertical difference b(r+1) - b(r-1)
   const int bL = from_left(b[3]), bR = from_right(b[0]);
-  S.sx[P][0] = b[1] - bL;
-  S.sx[P][1] = b[2] - b[0];
-  S.sx[P][2] = b[3] - b[1];
-  S.sx[P][3] = bR - b[2];
+  const int sxn[4] = {b[1] - bL, b[2] - b[0], b[3] - b[1], bR - b[2]};
   int gx[4], sy[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    S.u1[P][i] = S.sx[P][i] + S.sx[Q][i];
-    gx[i] = S.u1[P][i] + S.u1[Q][i];
+    gx[i] = S.sx[P][i] + 2 * S.sx[Q][i] + sxn[i];          // (1 2 1) down the column
+    S.sx[P][i] = sxn[i];
     sy[i] = b[i] - S.b[P][i];          // the same parity slot still holds b(r-2)
     S.b[P][i] = b[i];
   }
@@ -989,7 +993,7 @@ __device__ void norm_chunk(const EdgeLaunch& L, const FlatItem& it, float med) {
 __device__ __forceinline__ int refine_digit_bits(int prec) { return prec == IGSP_FP16 ? 3 : 8; }
 
 template <int PREC, int NW>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(IGSP_FUSED_WAVES_PER_EU))) void
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(IGSP_PERSIST_WAVES_PER_EU))) void
 edge_persistent_kernel(EdgeLaunch L, PersistLaunch P) {
   constexpr int NT = NW * 64;
   constexpr int NB = Keys<PREC>::bins;
