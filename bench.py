@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--wg-waves", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-view FP32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-unfused", action="store_true",
+                    help="skip the unfused (one launch per step) form of the same batch")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     ap.add_argument("--stage-reps", type=int, default=10)
     ap.add_argument("--tune", action="store_true",
@@ -335,6 +337,18 @@ def main():
     achieved = fused_bytes / (stage_ms["fused"] * 1e-3) / 1e9
     log(f"stages: {stage_ms}, las {las_ms}")
 
+    # ---- the paper's unfused layout on the same batch and storage precision
+    unfused = None
+    if not args.no_unfused:
+        def run_unfused():
+            igsp.edge_importance(img, views, out, precision=prec, batched="unfused", stream=stream)
+        ums, _ = timed(run_unfused, 1, max(1, min(args.steps, 5)))
+        unfused = {"form": f"unfused batched {prec} (gray, blur, Sobel, suppression as separate launches)",
+                   "edge_ms": round(ums, 4), "mpx_per_s": round(mpx / (ums * 1e-3), 1),
+                   "fused_edge_speedup": round(ums / stage_ms["edge"], 3)}
+        log(f"unfused edge maps: {ums:.3f} ms")
+        igsp.release_plans()   # frees the unfused form's per-step buffers
+
     # ---- practical ceiling of a read+write stream: a plain device copy
     cbytes = 1 << 30
     csrc = torch.empty(cbytes, dtype=torch.uint8, device=dev)
@@ -451,6 +465,8 @@ def main():
         las_bytes = N0 + 120 * K
         res["las"] = {"ms": round(las_ms, 4), "gaussians_split_per_s": round(K / (las_ms * 1e-3), 1),
                       "algorithmic_GBps": round(las_bytes / (las_ms * 1e-3) / 1e9, 1)}
+    if unfused:
+        res["unfused"] = unfused
     if plain:
         res["plain_fp32"] = plain
         res["speedup_vs_plain_fp32"] = round(plain["ms_per_step"] / ms, 3)

@@ -81,9 +81,14 @@ typedef enum {
   IGSP_BATCHED = 1,             /* every view together; the library picks the
                                    form below (tuned, else staged)            */
   IGSP_BATCHED_STAGED = 2,      /* every view in one launch per stage         */
-  IGSP_BATCHED_PERSISTENT = 3   /* every view and stage in one persistent
+  IGSP_BATCHED_PERSISTENT = 3,  /* every view and stage in one persistent
                                    launch; later stages of earlier views run
                                    beside the stencil pass of later ones      */
+  IGSP_UNFUSED = 4              /* the paper's layout, for comparison: gray,
+                                   blur, Sobel and suppression as separate
+                                   launches over every view, each step's
+                                   result in HBM (16 B/px of extra plan
+                                   memory); never chosen by IGSP_BATCHED     */
 } igsp_form;
 
 typedef struct {

@@ -153,14 +153,15 @@ def _need(t, dtype, name):
     _ = torch
 
 
-PLAIN, BATCHED, BATCHED_STAGED, BATCHED_PERSISTENT = 0, 1, 2, 3
-FORMS = {"plain": PLAIN, "batched": BATCHED, "staged": BATCHED_STAGED, "persistent": BATCHED_PERSISTENT}
+PLAIN, BATCHED, BATCHED_STAGED, BATCHED_PERSISTENT, UNFUSED = 0, 1, 2, 3, 4
+FORMS = {"plain": PLAIN, "batched": BATCHED, "staged": BATCHED_STAGED, "persistent": BATCHED_PERSISTENT,
+         "unfused": UNFUSED}
 FORM_NAMES = {v: k for k, v in FORMS.items()}
 
 
 def form_code(batched) -> int:
     """Launch form: True / "batched" (library's choice), False / "plain",
-    "staged", "persistent", or the integer code."""
+    "staged", "persistent", "unfused", or the integer code."""
     if isinstance(batched, str):
         return FORMS[batched]
     if isinstance(batched, bool):

@@ -200,6 +200,44 @@ __device__ __forceinline__ void gray4(uint32_t d0, uint32_t d1, uint32_t d2, int
   g[3] = (int)(lo3 + (hi3 << 8));
 }
 
+// ------------------------------------------------------------- suppression
+
+// Orientation of a gradient: within 22.5 degrees of the x axis (cH), of the
+// y axis (cV), else diagonal, (1,1) if gx and gy have equal signs (c45),
+// else (1,-1); tan 22.5 = sqrt 2 - 1. sgn = -1 if the gradient points along
+// -e for the bin's axis e, else 0.
+struct Dir {
+  bool cH, cV, c45;
+  int sgn;
+};
+
+constexpr float kTan = 0.41421356237309503f;
+
+__device__ __forceinline__ Dir direction(float fx, float fy) {
+  const float ax = __builtin_fabsf(fx), ay = __builtin_fabsf(fy);
+  Dir d;
+  d.cH = ay < kTan * ax;
+  d.cV = ax < kTan * ay;
+  d.c45 = (__float_as_int(fx) ^ __float_as_int(fy)) >= 0;
+  d.sgn = (d.cV ? __float_as_int(fy) : __float_as_int(fx)) >> 31;
+  return d;
+}
+
+// keep iff M(p) > M(p - d) and M(p) >= M(p + d) and M(p) > 0, d = +e or -e.
+// Magnitudes are non-negative floats, so they order as their bit patterns,
+// and "m > x" is "m >= the next float after x" = bits(x) + 1: one unsigned
+// compare against a maximum decides the pixel. U*, C*, D* are the
+// magnitudes of the row above, this row and the row below (l, c, r columns).
+__device__ __forceinline__ bool keep_of(const Dir& d, float m, float Ul, float Uc, float Ur, float Cl, float Cr,
+                                        float Dl, float Dc, float Dr) {
+  // A = p - e, B = p + e for the axis e of the bin: x, y, (1,1), (1,-1)
+  const float A = d.cH ? Cl : (d.cV ? Uc : (d.c45 ? Ul : Dl));
+  const float B = d.cH ? Cr : (d.cV ? Dc : (d.c45 ? Dr : Ur));
+  const uint32_t bA = __float_as_uint(A) + 1u + (uint32_t)d.sgn;  // strict unless d = -e
+  const uint32_t bB = __float_as_uint(B) - (uint32_t)d.sgn;       // strict if d = -e
+  return __float_as_uint(m) >= max(max(bA, bB), 1u);
+}
+
 // ------------------------------------------------------------- stage 1
 
 // Loop-carried state of one wavefront's march down its strip. Depth-one
@@ -320,7 +358,6 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   // ---- 6. suppression of row c = yy-4: up = M[MU], centre = M[MC], down = M[MD]
   // (rows before the strip's first output are computed too and their stores
   // dropped, so the loop body has no branch around memory operations)
-  const float kTan = 0.41421356237309503f;  // tan(22.5 deg) = sqrt(2) - 1
   const int c = C.ys - 2 * kHalo + t;
   const bool row_out = t >= 2 * kHalo && t < C.T;
   const float* Mu = S.M[MU];
@@ -332,25 +369,8 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
     const float Ul = i > 0 ? Mu[i - 1] : S.ML[MU], Uc = Mu[i], Ur = i < 3 ? Mu[i + 1] : S.MR[MU];
     const float Cl = i > 0 ? Mc[i - 1] : S.ML[MC], Cr = i < 3 ? Mc[i + 1] : S.MR[MC];
     const float Dl = i > 0 ? Md[i - 1] : S.ML[MD], Dc = Md[i], Dr = i < 3 ? Md[i + 1] : S.MR[MD];
-    // orientation bin: within 22.5 degrees of the x axis, of the y axis, or
-    // diagonal (gx, gy of equal sign: (1,1), else (1,-1)); tan 22.5 = sqrt 2 - 1
-    const float fx = S.fx[Q][i], fy = S.fy[Q][i];
-    const float ax = __builtin_fabsf(fx), ay = __builtin_fabsf(fy);
-    const bool cH = ay < kTan * ax;
-    const bool cV = ax < kTan * ay;
-    const bool c45 = (__float_as_int(fx) ^ __float_as_int(fy)) >= 0;
-    // A = p - e, B = p + e for the axis e of the bin: x, y, (1,1), (1,-1)
-    const float A = cH ? Cl : (cV ? Uc : (c45 ? Ul : Dl));
-    const float B = cH ? Cr : (cV ? Dc : (c45 ? Dr : Ur));
     const float m = Mc[i];
-    // keep iff M(p) > M(p - d) and M(p) >= M(p + d) and M(p) > 0, d = +e or
-    // -e by the sign of the gradient's component along e. Magnitudes are
-    // non-negative floats, so they order as their bit patterns and "m > x"
-    // is "m >= next float after x" = bits(x) + 1: one unsigned max-compare.
-    const int sgn = (cV ? __float_as_int(fy) : __float_as_int(fx)) >> 31;  // -1 if d = -e, else 0
-    const uint32_t bA = __float_as_uint(A) + 1u + (uint32_t)sgn;           // strict unless d = -e
-    const uint32_t bB = __float_as_uint(B) - (uint32_t)sgn;                // strict if d = -e
-    const bool keep = __float_as_uint(m) >= max(max(bA, bB), 1u);
+    const bool keep = keep_of(direction(S.fx[Q][i], S.fy[Q][i]), m, Ul, Uc, Ur, Cl, Cr, Dl, Dc, Dr);
     const float v = St::kSquare ? m : __builtin_amdgcn_sqrtf(m) * kStoreScaleRoot;
     q[i] = keep ? v : 0.0f;
   }
@@ -701,6 +721,126 @@ __global__ __launch_bounds__(256) void normalise_kernel(EdgeLaunch L, int flat0)
       for (int i = 1; i < 8; ++i) ek = k == i ? e[i] : ek;
       as_global(outp)[p + k] = ek;
     }
+  }
+}
+
+// ------------------------------------------------------------- unfused form
+//
+// The paper's kernel layout on this GPU, kept as an ablation of the fusion:
+// gray, the 5x5 blur (direct 25-tap sum), Sobel magnitude and orientation,
+// and suppression are separate launches, each reading the previous step's
+// result from HBM. Same integer and FP32 arithmetic as the fused stencil
+// (shared direction and decision functions), so the maps agree bit for bit.
+
+__device__ __forceinline__ int refl(int i, int n) { return fold_near(i, n); }
+
+__global__ __launch_bounds__(kUfCols) void uf_gray_kernel(EdgeLaunch L, UfLaunch U) {
+  const UfItem it = U.items[blockIdx.x];
+  const ViewDesc vd = L.views[it.view];
+  const int x = it.x0 + threadIdx.x;
+  if (x >= vd.W) return;
+  const int y1 = min(it.y0 + kUfRows, vd.H);
+  for (int y = it.y0; y < y1; ++y) {
+    const int64_t p = (int64_t)y * vd.W + x;
+    const uint8_t* px = L.images + vd.in_off + 3 * p;
+    U.gray[vd.map_off + p] = 299 * (int)px[0] + 587 * (int)px[1] + 114 * (int)px[2];
+  }
+}
+
+__global__ __launch_bounds__(kUfCols) void uf_blur_kernel(EdgeLaunch L, UfLaunch U) {
+  const UfItem it = U.items[blockIdx.x];
+  const ViewDesc vd = L.views[it.view];
+  const int x = it.x0 + threadIdx.x;
+  if (x >= vd.W) return;
+  const int w[5] = {1, 4, 6, 4, 1};
+  int xs[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) xs[k] = refl(x + k - 2, vd.W);
+  const int32_t* g = U.gray + vd.map_off;
+  const int y1 = min(it.y0 + kUfRows, vd.H);
+  for (int y = it.y0; y < y1; ++y) {
+    int acc = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int32_t* row = g + (int64_t)refl(y + j - 2, vd.H) * vd.W;
+      int h = 0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) h += w[k] * row[xs[k]];
+      acc += w[j] * h;
+    }
+    U.blur[vd.map_off + (int64_t)y * vd.W + x] = acc;
+  }
+}
+
+__global__ __launch_bounds__(kUfCols) void uf_sobel_kernel(EdgeLaunch L, UfLaunch U) {
+  const UfItem it = U.items[blockIdx.x];
+  const ViewDesc vd = L.views[it.view];
+  const int x = it.x0 + threadIdx.x;
+  if (x >= vd.W) return;
+  const int xl = refl(x - 1, vd.W), xr = refl(x + 1, vd.W);
+  const int32_t* b = U.blur + vd.map_off;
+  const int y1 = min(it.y0 + kUfRows, vd.H);
+  for (int y = it.y0; y < y1; ++y) {
+    const int32_t* ru = b + (int64_t)refl(y - 1, vd.H) * vd.W;
+    const int32_t* rc = b + (int64_t)y * vd.W;
+    const int32_t* rd = b + (int64_t)refl(y + 1, vd.H) * vd.W;
+    const int gx = (ru[xr] - ru[xl]) + 2 * (rc[xr] - rc[xl]) + (rd[xr] - rd[xl]);
+    const int gy = (rd[xl] - ru[xl]) + 2 * (rd[x] - ru[x]) + (rd[xr] - ru[xr]);
+    const float fx = (float)gx, fy = (float)gy;
+    const int64_t p = vd.map_off + (int64_t)y * vd.W + x;
+    U.mag[p] = __builtin_fmaf(fx, fx, fy * fy);
+    const Dir d = direction(fx, fy);
+    U.code[p] = (uint8_t)((d.cH ? 1 : 0) | (d.cV ? 2 : 0) | (d.c45 ? 4 : 0) | (d.sgn ? 8 : 0));
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kUfCols) void uf_nms_kernel(EdgeLaunch L, UfLaunch U) {
+  using St = Store<PREC>;
+  constexpr int NB = Keys<PREC>::bins;
+  __shared__ uint32_t hist[NB];
+  for (int i = threadIdx.x; i < NB; i += kUfCols) hist[i] = 0;
+  __syncthreads();
+  const UfItem it = U.items[blockIdx.x];
+  const ViewDesc vd = L.views[it.view];
+  const int x = it.x0 + threadIdx.x;
+  if (x < vd.W) {
+    const int xl = refl(x - 1, vd.W), xr = refl(x + 1, vd.W);
+    const float* M = U.mag + vd.map_off;
+    typename St::T* out = reinterpret_cast<typename St::T*>(L.map) + vd.map_off;
+    const int y1 = min(it.y0 + kUfRows, vd.H);
+    for (int y = it.y0; y < y1; ++y) {
+      const float* ru = M + (int64_t)refl(y - 1, vd.H) * vd.W;
+      const float* rc = M + (int64_t)y * vd.W;
+      const float* rd = M + (int64_t)refl(y + 1, vd.H) * vd.W;
+      const uint8_t c = U.code[vd.map_off + (int64_t)y * vd.W + x];
+      Dir d;
+      d.cH = c & 1;
+      d.cV = (c >> 1) & 1;
+      d.c45 = (c >> 2) & 1;
+      d.sgn = (c & 8) ? -1 : 0;
+      const float m = rc[x];
+      const bool keep = keep_of(d, m, ru[xl], ru[x], ru[xr], rc[xl], rc[xr], rd[xl], rd[x], rd[xr]);
+      const float v = St::kSquare ? m : __builtin_amdgcn_sqrtf(m) * kStoreScaleRoot;
+      const float q = keep ? v : 0.0f;
+      uint32_t bits;
+      if constexpr (PREC == IGSP_FP32) {
+        out[(int64_t)y * vd.W + x] = q;
+        bits = __float_as_uint(q);
+      } else {
+        const uint16_t h = (uint16_t)(St::pack2(q, 0.0f) & 0xFFFFu);
+        out[(int64_t)y * vd.W + x] = h;
+        bits = __float_as_uint(St::widen(h));
+      }
+      if (bits != 0u)
+        atomicAdd(&hist[min(max((int)(bits >> 16) - (int)Keys<PREC>::lo, 0), NB - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t* gh = L.hist + (int64_t)it.view * kBinsMax;
+  for (int i = threadIdx.x; i < NB; i += kUfCols) {
+    const uint32_t c = hist[i];
+    if (c) atomicAdd(gh + i, c);
   }
 }
 
@@ -1121,6 +1261,20 @@ int persistent_blocks_per_cu(int precision, int wg_waves) {
     case IGSP_BF16: return blocks_per_cu_for_prec<IGSP_BF16>(wg_waves);
     default: return blocks_per_cu_for_prec<IGSP_FP32>(wg_waves);
   }
+}
+
+hipError_t launch_edge_unfused(const EdgeLaunch& L, const UfLaunch& U, hipStream_t s) {
+  if (U.n_items <= 0) return hipSuccess;
+  const dim3 g(U.n_items), b(kUfCols);
+  hipLaunchKernelGGL(uf_gray_kernel, g, b, 0, s, L, U);
+  hipLaunchKernelGGL(uf_blur_kernel, g, b, 0, s, L, U);
+  hipLaunchKernelGGL(uf_sobel_kernel, g, b, 0, s, L, U);
+  switch (L.precision) {
+    case IGSP_FP16: hipLaunchKernelGGL(uf_nms_kernel<IGSP_FP16>, g, b, 0, s, L, U); break;
+    case IGSP_BF16: hipLaunchKernelGGL(uf_nms_kernel<IGSP_BF16>, g, b, 0, s, L, U); break;
+    default: hipLaunchKernelGGL(uf_nms_kernel<IGSP_FP32>, g, b, 0, s, L, U); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_median_select(const EdgeLaunch& L, int v0, int nv, hipStream_t s) {

@@ -91,10 +91,15 @@ struct EdgePlan {
   PViewSync* d_sync = nullptr;
   PCtl* d_ctl = nullptr;
   int n_tasks = 0, grid = 0, lag = 0;
+  // unfused form (built on first use): its tiles and per-step buffers
+  UfLaunch uf{};
+  int64_t map_elems = 0;
   ~EdgePlan() {
     (void)hipFree(d_views); (void)hipFree(d_items); (void)hipFree(d_flat); (void)hipFree(d_map);
     (void)hipFree(d_hist); (void)hipFree(d_rhist); (void)hipFree(d_state);
     (void)hipFree(d_pflat); (void)hipFree(d_tasks); (void)hipFree(d_sync); (void)hipFree(d_ctl);
+    (void)hipFree(const_cast<UfItem*>(uf.items)); (void)hipFree(uf.gray); (void)hipFree(uf.blur);
+    (void)hipFree(uf.mag); (void)hipFree(uf.code);
   }
 };
 
@@ -230,6 +235,7 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
   }
   plan->item_begin[n] = (int)items.size();
   plan->flat_begin[n] = (int)flat.size();
+  plan->map_elems = map_elems;
   if (upload(&plan->d_views, vd) != hipSuccess || upload(&plan->d_items, items) != hipSuccess ||
       upload(&plan->d_flat, flat) != hipSuccess)
     return IGSP_ERR_HIP;
@@ -309,6 +315,33 @@ igsp_status ensure_persistent(EdgePlan* P) {
   return IGSP_OK;
 }
 
+// Tiles and per-step buffers of the unfused form (gray, blur: int32;
+// magnitude: float; orientation code: byte; all in the plan's map layout).
+igsp_status ensure_unfused(EdgePlan* P) {
+  if (P->uf.items) return IGSP_OK;
+  std::vector<UfItem> items;
+  for (int v = 0; v < P->n_views; ++v) {
+    const igsp_view& d = P->key.views[v];
+    for (int y0 = 0; y0 < d.height; y0 += kUfRows)
+      for (int x0 = 0; x0 < d.width; x0 += kUfCols) items.push_back(UfItem{v, x0, y0, 0});
+  }
+  UfItem* d_items = nullptr;
+  const size_t n = (size_t)std::max<int64_t>(P->map_elems, 64);
+  UfLaunch u{};
+  if (upload(&d_items, items) != hipSuccess || hipMalloc(reinterpret_cast<void**>(&u.gray), n * 4) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&u.blur), n * 4) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&u.mag), n * 4) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&u.code), n) != hipSuccess) {
+    (void)hipFree(d_items); (void)hipFree(u.gray); (void)hipFree(u.blur); (void)hipFree(u.mag);
+    (void)hipFree(u.code);
+    return IGSP_ERR_HIP;
+  }
+  u.items = d_items;
+  u.n_items = (int32_t)items.size();
+  P->uf = u;
+  return IGSP_OK;
+}
+
 // The concrete form of a call: plain per view, staged batched, or one
 // persistent launch. IGSP_BATCHED lets the library choose (tuned, else
 // staged).
@@ -340,16 +373,21 @@ igsp_status get_edge_plan(const igsp_view* views, int32_t n_views, const igsp_ed
   key.seg_rows = (opts && opts->seg_rows) ? opts->seg_rows : seg;
   key.wg_waves = (opts && opts->wg_waves) ? opts->wg_waves : wgw;
   key.views.assign(views, views + n_views);
-  const bool persistent = resolve_form(views, n_views, opts) == IGSP_BATCHED_PERSISTENT;
+  const int form = resolve_form(views, n_views, opts);
+  auto extras = [form](EdgePlan* P) -> igsp_status {
+    if (form == IGSP_BATCHED_PERSISTENT) return ensure_persistent(P);
+    if (form == IGSP_UNFUSED) return ensure_unfused(P);
+    return IGSP_OK;
+  };
   for (auto it = g_edge_plans.begin(); it != g_edge_plans.end(); ++it) {
     if ((*it)->key == key) {
       g_edge_plans.splice(g_edge_plans.begin(), g_edge_plans, it);
       *out = g_edge_plans.front();
-      return persistent ? ensure_persistent(out->get()) : IGSP_OK;
+      return extras(out->get());
     }
   }
   st = build_edge_plan(key, out);
-  if (st == IGSP_OK && persistent) st = ensure_persistent(out->get());
+  if (st == IGSP_OK) st = extras(out->get());
   return st;
 }
 
@@ -410,6 +448,14 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
     LP.flat = P->d_pflat;
     e = launch_edge_persistent(LP, PL, P->grid, s);
     for (int k = 1; k < 4 && e == hipSuccess; ++k) e = mark(k, s);
+  } else if (e == hipSuccess && form == IGSP_UNFUSED) {
+    if (!P->uf.items) return IGSP_ERR_HIP;  // buffers are built with the plan
+    e = launch_edge_unfused(L, P->uf, s);
+    if (e == hipSuccess) e = mark(1, s);
+    if (e == hipSuccess) e = tail(0, n, s);
+    if (e == hipSuccess) e = mark(2, s);
+    if (e == hipSuccess) e = norm(0, n, s);
+    if (e == hipSuccess) e = mark(3, s);
   } else if (e == hipSuccess && batched) {
     e = stencil(0, n, s);
     if (e == hipSuccess) e = mark(1, s);

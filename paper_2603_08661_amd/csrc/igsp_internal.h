@@ -124,6 +124,24 @@ struct PersistLaunch {
   int32_t levels;    // refinement passes: BF16 0, FP16 1, FP32 2
 };
 
+// The unfused form (the paper's layout, kept as an ablation): one kernel per
+// step over tiles of 256 columns x kUfRows rows, each step's result in HBM.
+constexpr int kUfCols = 256;
+constexpr int kUfRows = 32;
+
+struct UfItem {
+  int32_t view, x0, y0, pad;
+};
+
+struct UfLaunch {
+  const UfItem* items;
+  int32_t n_items;
+  int32_t* gray;     // 299 R + 587 G + 114 B, per pixel (plan map layout)
+  int32_t* blur;     // 5x5 binomial blur x 256000
+  float* mag;        // squared Sobel magnitude
+  uint8_t* code;     // orientation: bit 0 cH, bit 1 cV, bit 2 c45, bit 3 gradient along -e
+};
+
 // Enqueue each stage over the given ranges (item ranges index the plan's
 // tables; view ranges are [v0, v1)).
 hipError_t launch_edge_fused(const EdgeLaunch& L, int item0, int n_items, hipStream_t s);
@@ -132,6 +150,10 @@ hipError_t launch_median_refine(const EdgeLaunch& L, int flat0, int n_flat, int 
 hipError_t launch_refine_select(const EdgeLaunch& L, int v0, int nv, int digit_bits, int final_shift,
                                 hipStream_t s);
 hipError_t launch_normalise(const EdgeLaunch& L, int flat0, int n_flat, hipStream_t s);
+// The stencil steps of the unfused form: gray, blur, Sobel, suppression
+// (+ histogram), four launches; the median and normalisation follow as in the
+// staged form.
+hipError_t launch_edge_unfused(const EdgeLaunch& L, const UfLaunch& U, hipStream_t s);
 // The whole batched pipeline as one launch of `grid` persistent work-groups.
 hipError_t launch_edge_persistent(const EdgeLaunch& L, const PersistLaunch& P, int grid, hipStream_t s);
 // Work-groups of the persistent kernel resident per compute unit.

@@ -17,7 +17,7 @@ igsp_status validate_edge(const uint8_t* images, const igsp_view* views, int32_t
   if ((reinterpret_cast<uintptr_t>(images) & 15u) != 0) return IGSP_ERR_ALIGN;
   if (opts) {
     if (opts->precision < IGSP_FP32 || opts->precision > IGSP_BF16) return IGSP_ERR_PARAM;
-    if (opts->batched < IGSP_PLAIN || opts->batched > IGSP_BATCHED_PERSISTENT) return IGSP_ERR_PARAM;
+    if (opts->batched < IGSP_PLAIN || opts->batched > IGSP_UNFUSED) return IGSP_ERR_PARAM;
     if (opts->seg_rows != 0 && (opts->seg_rows < 8 || opts->seg_rows > 4096)) return IGSP_ERR_PARAM;
     const int w = opts->wg_waves;
     if (w != 0 && w != 1 && w != 2 && w != 4 && w != 8) return IGSP_ERR_PARAM;

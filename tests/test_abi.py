@@ -69,7 +69,7 @@ def test_edge_validation(views, n, kw, code):
     assert edge(views, n, **kw) == code
 
 
-@pytest.mark.parametrize("field,val", [("precision", 3), ("precision", -1), ("batched", 4), ("batched", -1), ("seg_rows", 4),
+@pytest.mark.parametrize("field,val", [("precision", 3), ("precision", -1), ("batched", 5), ("batched", -1), ("seg_rows", 4),
                                        ("seg_rows", 5000), ("wg_waves", 3), ("wg_waves", 16)])
 def test_edge_bad_options(field, val):
     o = B.EdgeOpts(0, 1, 0, 0, None, None, None)

@@ -35,7 +35,7 @@ def test_workload1_single_view(precision):
         print(precision, form, st)
 
 
-@pytest.mark.parametrize("form", BATCHED_FORMS)
+@pytest.mark.parametrize("form", BATCHED_FORMS + ["unfused"])
 @pytest.mark.parametrize("precision", PRECS)
 def test_ragged_views_unaligned(precision, form):
     vb = small_batch()
@@ -87,7 +87,8 @@ def test_forms_equal_and_deterministic(precision):
     vb = small_batch(in_align=16, out_align=4)
     a = gpu_edge(vb, precision, "staged")
     others = [gpu_edge(vb, precision, "plain"), gpu_edge(vb, precision, "persistent"),
-              gpu_edge(vb, precision, "persistent", reps=4), gpu_edge(vb, precision, "staged", reps=3)]
+              gpu_edge(vb, precision, "persistent", reps=4), gpu_edge(vb, precision, "staged", reps=3),
+              gpu_edge(vb, precision, "unfused"), gpu_edge(vb, precision, "unfused", reps=2)]
     for y in others:
         for u, v in zip(a, y):
             assert (u == v).all()
