@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--wg-waves", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-view FP32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-las-full", action="store_true",
+                    help="skip the full-record split (48 features + Adam moments)")
     ap.add_argument("--no-unfused", action="store_true",
                     help="skip the unfused (one launch per step) form of the same batch")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
@@ -337,6 +339,42 @@ def main():
     achieved = fused_bytes / (stage_ms["fused"] * 1e-3) / 1e9
     log(f"stages: {stage_ms}, las {las_ms}")
 
+    # ---- the full-record split a trainer calls: 48 feature floats per row
+    #      and both Adam moments of every parameter group (same N, K, mask)
+    las_full = None
+    if has_las and not args.no_las_full:
+        F = 48
+        reps = 5
+        capf = N0 + K * (reps + 1)
+        widths = {"means": 3, "log_scales": 3, "quats": 4, "opacity_logits": 1, "features": F}
+        Gf = {}
+        for k in ("means", "log_scales", "quats", "opacity_logits"):
+            a = getattr(g, k)
+            Gf[k] = torch.zeros((capf,) + a.shape[1:], dtype=torch.float32, device=dev)
+            Gf[k][:N0] = torch.from_numpy(a).to(dev)
+        Gf["features"] = torch.randn((capf, F), dtype=torch.float32, device=dev)
+        mom = {grp: tuple(torch.randn((capf, w) if w > 1 else (capf,), dtype=torch.float32, device=dev)
+                          for _ in range(2)) for grp, w in widths.items()}
+        cnt = torch.tensor([N0], dtype=torch.int64, device=dev)
+        maskf = torch.zeros(capf, dtype=torch.uint8, device=dev)
+        maskf[:N0] = torch.from_numpy(mk).to(dev)
+        sidxf = torch.zeros(capf, dtype=torch.int32, device=dev)
+        stf = torch.zeros(1, dtype=torch.int32, device=dev)
+
+        def run_full():
+            igsp.long_axis_split_full(Gf["means"], Gf["log_scales"], Gf["quats"], Gf["opacity_logits"], cnt,
+                                      maskf, sidxf, stf, mom, features=Gf["features"], stream=stream)
+        fms, _ = timed(run_full, 1, reps)
+        assert int(stf.item()) == 0, "full-record split reported a capacity error"
+        per_split = (44 + 4 * F) + (28 + 44 + 4 * F + 4) + 2 * 2 * 4 * sum(widths.values())
+        fbytes = N0 + per_split * K
+        las_full = {"feat_dim": F, "adam_moments": "m and v of all five groups", "ms": round(fms, 4),
+                    "gaussians_split_per_s": round(K / (fms * 1e-3), 1),
+                    "algorithmic_bytes": int(fbytes),
+                    "algorithmic_GBps": round(fbytes / (fms * 1e-3) / 1e9, 1)}
+        log(f"full-record split: {fms:.3f} ms")
+        del Gf, mom, maskf, sidxf
+
     # ---- the paper's unfused layout on the same batch and storage precision
     unfused = None
     if not args.no_unfused:
@@ -465,6 +503,8 @@ def main():
         las_bytes = N0 + 120 * K
         res["las"] = {"ms": round(las_ms, 4), "gaussians_split_per_s": round(K / (las_ms * 1e-3), 1),
                       "algorithmic_GBps": round(las_bytes / (las_ms * 1e-3) / 1e9, 1)}
+    if las_full:
+        res["las_full_record"] = las_full
     if unfused:
         res["unfused"] = unfused
     if plain:

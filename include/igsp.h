@@ -218,6 +218,33 @@ typedef struct {
 igsp_status long_axis_split(const igsp_gaussians* g, const uint8_t* mask, const igsp_las_out* out,
                             const igsp_las_params* params, void* stream);
 
+/*
+ * Adam moments kept by the caller's optimiser for each parameter group, in
+ * the same row layout as the parameters (device, float32, `capacity` rows).
+ * [0] = first moment, [1] = second moment; any pointer may be NULL (that
+ * state is not kept).
+ */
+typedef struct {
+  float* means[2];            /* [capacity][3]        */
+  float* log_scales[2];       /* [capacity][3]        */
+  float* quats[2];            /* [capacity][4]        */
+  float* opacity_logits[2];   /* [capacity]           */
+  float* features[2];         /* [capacity][feat_dim] */
+} igsp_adam_moments;
+
+/*
+ * The full-record split a trainer calls: long_axis_split (same arguments and
+ * result, features of any width copied to the second child) plus the
+ * optimiser state of both children. The paper does not say what happens to
+ * optimiser state; the reading taken here is the usual one for a split that
+ * replaces a parent by two new Gaussians: every given moment row of both
+ * children (rows i and N + r) is set to 0, all other rows are untouched.
+ * adam (host, optional) NULL = no optimiser state, i.e. long_axis_split.
+ * Same all-or-nothing rule: on IGSP_ERR_CAPACITY no moment row changes.
+ */
+igsp_status long_axis_split_full(const igsp_gaussians* g, const igsp_adam_moments* adam, const uint8_t* mask,
+                                 const igsp_las_out* out, const igsp_las_params* params, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* One densification step as a HIP graph                                    */
 /* ------------------------------------------------------------------------ */

@@ -131,6 +131,25 @@ def opacity_update(o: float, beta: float = BETA) -> float:
     return float(lib().orc_opacity(float(o), float(beta)))
 
 
+def las_moments(N: int, split_idx, moments: dict) -> dict:
+    """Optimiser state after the full-record split (FP64 copies).
+
+    The paper does not say what happens to optimiser state; the reading taken
+    (and stated with the GPU entry point) is the usual one for a split that
+    replaces a parent by two new Gaussians: the moment rows of both children
+    -- row i of every split Gaussian and rows N .. N + K - 1 -- become 0,
+    every other row keeps its value.
+    """
+    idx = np.asarray(split_idx, np.int64)
+    out = {}
+    for k, a in moments.items():
+        b = np.array(a, dtype=np.float64, copy=True)
+        b[idx] = 0.0
+        b[N:N + idx.size] = 0.0
+        out[k] = b
+    return out
+
+
 def las(N: int, means, log_scales, quats, opacity_logits, mask, feats=None,
         alpha: float = ALPHA, gamma: float = GAMMA, beta: float = BETA) -> dict:
     """Long-Axis-Split in place over arrays of `capacity` rows (FP64 results).

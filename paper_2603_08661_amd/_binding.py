@@ -25,7 +25,8 @@ STATUS = {
 }
 
 # Every symbol include/igsp.h declares.
-EXPORTS = ("edge_importance", "long_axis_split", "igsp_edge_autotune", "igsp_edge_resolve", "igsp_step_create",
+EXPORTS = ("edge_importance", "long_axis_split", "long_axis_split_full", "igsp_edge_autotune", "igsp_edge_resolve",
+           "igsp_step_create",
            "igsp_step_launch", "igsp_step_destroy", "igsp_status_string", "igsp_release_plans", "igsp_version")
 
 # Tile shapes and launch forms the autotuner picked on MI355X for the
@@ -63,6 +64,10 @@ class LasParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_float), ("gamma", ctypes.c_float), ("beta", ctypes.c_float)]
 
 
+class AdamMoments(ctypes.Structure):
+    _fields_ = [(g, ctypes.c_void_p * 2) for g in ("means", "log_scales", "quats", "opacity_logits", "features")]
+
+
 class LasOut(ctypes.Structure):
     _fields_ = [("split_idx", ctypes.c_void_p), ("status", ctypes.c_void_p), ("n_split", ctypes.c_void_p)]
 
@@ -88,6 +93,9 @@ def lib():
         L.long_axis_split.argtypes = [ctypes.POINTER(Gaussians), vp, ctypes.POINTER(LasOut),
                                       ctypes.POINTER(LasParams), vp]
         L.long_axis_split.restype = i32
+        L.long_axis_split_full.argtypes = [ctypes.POINTER(Gaussians), ctypes.POINTER(AdamMoments), vp,
+                                           ctypes.POINTER(LasOut), ctypes.POINTER(LasParams), vp]
+        L.long_axis_split_full.restype = i32
         L.igsp_edge_autotune.argtypes = [vp, ctypes.POINTER(View), i32, vp, i32, i32, ctypes.POINTER(EdgeOpts), vp]
         L.igsp_edge_autotune.restype = i32
         L.igsp_edge_resolve.argtypes = [ctypes.POINTER(View), i32, ctypes.POINTER(EdgeOpts)]
@@ -299,6 +307,43 @@ def long_axis_split(means, log_scales, quats, opacity_logits, count, mask, split
     prm = las_params(alpha, gamma, beta)
     _check(lib().long_axis_split(ctypes.byref(g), _ptr(mask), ctypes.byref(out), ctypes.byref(prm),
                                  _stream(stream)), "long_axis_split")
+
+
+ADAM_GROUPS = ("means", "log_scales", "quats", "opacity_logits", "features")
+
+
+def long_axis_split_full(means, log_scales, quats, opacity_logits, count, mask, split_idx, status, moments,
+                         n_split=None, features=None, alpha=0.5, gamma=0.85, beta=0.6, stream=None):
+    """The full-record split: long_axis_split plus the optimiser state.
+
+    moments: {group: (m, v)} for groups in ADAM_GROUPS, each tensor in the
+    group's row layout (either of the pair may be None); both children's
+    moment rows are cleared.
+    """
+    import torch
+
+    _need(mask, torch.uint8, "mask")
+    _need(split_idx, torch.int32, "split_idx")
+    _need(status, torch.int32, "status")
+    _need(n_split, torch.int64, "n_split")
+    g = gaussians_struct(means, log_scales, quats, opacity_logits, count, features)
+    if mask.numel() < g.capacity or split_idx.numel() < g.capacity:
+        raise ValueError("mask and split_idx need capacity entries")
+    widths = {"means": 3, "log_scales": 3, "quats": 4, "opacity_logits": 1, "features": g.feat_dim}
+    ptrs = {}
+    for grp, pair in (moments or {}).items():
+        if grp not in widths:
+            raise ValueError(f"unknown moment group {grp}")
+        for k, t in enumerate(pair):
+            _need(t, torch.float32, f"moments[{grp}][{k}]")
+            if t is not None and t.numel() < g.capacity * widths[grp]:
+                raise ValueError(f"moments[{grp}][{k}] needs {g.capacity} x {widths[grp]} floats")
+        ptrs[grp] = (ctypes.c_void_p * 2)(*[_ptr(t) for t in pair])
+    adam = AdamMoments(*[ptrs.get(grp, (ctypes.c_void_p * 2)(None, None)) for grp in ADAM_GROUPS])
+    out = LasOut(_ptr(split_idx), _ptr(status), _ptr(n_split))
+    prm = las_params(alpha, gamma, beta)
+    _check(lib().long_axis_split_full(ctypes.byref(g), ctypes.byref(adam), _ptr(mask), ctypes.byref(out),
+                                      ctypes.byref(prm), _stream(stream)), "long_axis_split_full")
 
 
 class Step:

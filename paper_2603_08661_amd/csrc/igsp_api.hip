@@ -508,11 +508,13 @@ igsp_status get_las_plan(int64_t capacity, std::shared_ptr<LasPlan>* out) {
   return IGSP_OK;
 }
 
-igsp_status enqueue_las(LasPlan* P, const igsp_gaussians* g, const uint8_t* mask, const igsp_las_out* out,
-                        const igsp_las_params* p, hipStream_t s) {
+igsp_status enqueue_las(LasPlan* P, const igsp_gaussians* g, const igsp_adam_moments* adam, const uint8_t* mask,
+                        const igsp_las_out* out, const igsp_las_params* p, hipStream_t s) {
   const double a = p ? p->alpha : 0.5, gm = p ? p->gamma : 0.85, b = p ? p->beta : 0.6;
   LasLaunch L;
   L.g = *g;
+  L.adam = adam ? *adam : igsp_adam_moments{};
+  if (g->feat_dim == 0) L.adam.features[0] = L.adam.features[1] = nullptr;
   L.mask = mask;
   L.split_idx = out->split_idx;
   L.status = out->status;
@@ -556,14 +558,26 @@ extern "C" igsp_status long_axis_split(const igsp_gaussians* g, const uint8_t* m
   std::shared_ptr<LasPlan> plan;
   st = get_las_plan(g->capacity, &plan);
   if (st != IGSP_OK) return st;
-  return enqueue_las(plan.get(), g, mask, out, params, static_cast<hipStream_t>(stream));
+  return enqueue_las(plan.get(), g, nullptr, mask, out, params, static_cast<hipStream_t>(stream));
+}
+
+extern "C" igsp_status long_axis_split_full(const igsp_gaussians* g, const igsp_adam_moments* adam,
+                                            const uint8_t* mask, const igsp_las_out* out,
+                                            const igsp_las_params* params, void* stream) {
+  igsp_status st = validate_las(g, mask, out, params);
+  if (st != IGSP_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::shared_ptr<LasPlan> plan;
+  st = get_las_plan(g->capacity, &plan);
+  if (st != IGSP_OK) return st;
+  return enqueue_las(plan.get(), g, adam, mask, out, params, static_cast<hipStream_t>(stream));
 }
 
 extern "C" igsp_status igsp_edge_resolve(const igsp_view* views, int32_t n_views, igsp_edge_opts* opts) {
   if (!opts || (n_views > 0 && !views)) return IGSP_ERR_NULL;
   if (n_views < 0) return IGSP_ERR_DIMS;
   if (opts->precision < IGSP_FP32 || opts->precision > IGSP_BF16) return IGSP_ERR_PARAM;
-  if (opts->batched < IGSP_PLAIN || opts->batched > IGSP_BATCHED_PERSISTENT) return IGSP_ERR_PARAM;
+  if (opts->batched < IGSP_PLAIN || opts->batched > IGSP_UNFUSED) return IGSP_ERR_PARAM;
   std::lock_guard<std::mutex> lk(g_mu);
   const int form = resolve_form(views, n_views, opts);
   int seg = default_seg_rows(), wgw = default_wg_waves();
@@ -686,7 +700,7 @@ extern "C" igsp_status igsp_step_create(const uint8_t* images, const igsp_view* 
     rs = IGSP_ERR_HIP;
   } else {
     if (eplan) rs = enqueue_edge(eplan.get(), images, ext.img_end, out_maps, opts, cs);
-    if (rs == IGSP_OK) rs = enqueue_las(lplan.get(), g, mask, out, params, cs);
+    if (rs == IGSP_OK) rs = enqueue_las(lplan.get(), g, nullptr, mask, out, params, cs);
     hipError_t e = hipStreamEndCapture(cs, &s->graph);
     if (rs == IGSP_OK && e != hipSuccess) rs = IGSP_ERR_HIP;
     if (rs == IGSP_OK && hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0) != hipSuccess)

@@ -175,6 +175,7 @@ struct LasScalars {
 
 struct LasLaunch {
   igsp_gaussians g;
+  igsp_adam_moments adam;    // all NULL for the plain split
   const uint8_t* mask;
   int32_t* split_idx;
   int32_t* status;

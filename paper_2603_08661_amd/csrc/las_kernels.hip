@@ -176,9 +176,41 @@ __device__ __forceinline__ void split_row(const LasLaunch& L, int64_t i, int64_t
   L.g.opacity_logits[i] = on;
   L.g.opacity_logits[j] = on;
   L.g.quats[4 * j] = qw; L.g.quats[4 * j + 1] = qx; L.g.quats[4 * j + 2] = qy; L.g.quats[4 * j + 3] = qz;
-  const int F = L.g.feat_dim;
-  for (int f = 0; f < F; ++f) L.g.features[j * F + f] = L.g.features[i * F + f];
   L.split_idx[rank] = (int32_t)i;
+}
+
+// Row-wide work for the `total` selected rows of a tile, spread over the
+// work-group with consecutive lanes on consecutive words of a row: the
+// second child's features copied from the parent, and the given moment rows
+// of both children cleared.
+__device__ __forceinline__ void zero_rows(float* a, int w, const int32_t* rows, int64_t base, int64_t N,
+                                          int64_t first, int total) {
+  if (!a) return;
+  for (int k = threadIdx.x; k < total * w; k += kLasThreads) {
+    const int r = k / w, e = k - r * w;
+    a[(base + rows[r]) * w + e] = 0.0f;
+    a[(N + first + r) * w + e] = 0.0f;
+  }
+}
+
+__device__ __forceinline__ void row_work(const LasLaunch& L, const int32_t* rows, int64_t base, int64_t N,
+                                         int64_t first, int total) {
+  const int F = L.g.feat_dim;
+  if (F > 0) {
+    float* f = L.g.features;
+    for (int k = threadIdx.x; k < total * F; k += kLasThreads) {
+      const int r = k / F, e = k - r * F;
+      f[(N + first + r) * F + e] = f[(base + rows[r]) * F + e];
+    }
+  }
+  const igsp_adam_moments& A = L.adam;
+  for (int m = 0; m < 2; ++m) {
+    zero_rows(A.means[m], 3, rows, base, N, first, total);
+    zero_rows(A.log_scales[m], 3, rows, base, N, first, total);
+    zero_rows(A.quats[m], 4, rows, base, N, first, total);
+    zero_rows(A.opacity_logits[m], 1, rows, base, N, first, total);
+    zero_rows(A.features[m], F, rows, base, N, first, total);
+  }
 }
 
 // Per live tile: the selected rows, compacted in ascending order into LDS
@@ -205,6 +237,7 @@ __global__ __launch_bounds__(kLasThreads) void las_split_kernel(LasLaunch L) {
       const int64_t rank = first + k;
       split_row(L, base + rows[k], N + rank, rank);
     }
+    row_work(L, rows, base, N, first, total);
     __syncthreads();  // rows[] is rewritten by the next tile
   }
 }

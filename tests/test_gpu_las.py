@@ -179,3 +179,77 @@ def test_two_calls_grow_count_on_device():
                     r1["quats"].astype(np.float32), r1["opacity_logits"].astype(np.float32), mk)
     assert r2["count"] == 1200
     assert np.abs(res["means"][:1200] - r2["means"][:1200]).max() < 1e-5
+
+
+def _run_full(g, N, mask, cap, F, seed, groups, over_capacity=False):
+    """long_axis_split_full with F feature floats and random moments for the
+    given groups; returns (result dict as run_las, moments before, after)."""
+    import torch
+
+    import paper_2603_08661_amd as igsp
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(seed)
+    widths = {"means": 3, "log_scales": 3, "quats": 4, "opacity_logits": 1, "features": F}
+    feats = rng.normal(size=(N, F)).astype(np.float32)
+
+    def padded(a, rows):
+        out = np.full((rows,) + a.shape[1:], CANARY, np.float32)
+        out[:min(rows, a.shape[0])] = a[:rows]
+        return out
+
+    host = {"means": padded(g.means, cap), "log_scales": padded(g.log_scales, cap),
+            "quats": padded(g.quats, cap), "opacity_logits": padded(g.opacity_logits, cap),
+            "features": padded(feats, cap)}
+    t = {k: torch.from_numpy(v.copy()).to(dev) for k, v in host.items()}
+    mom_host = {grp: [rng.normal(size=(cap, widths[grp])).astype(np.float32).squeeze(-1 if widths[grp] == 1 else ())
+                      for _ in range(2)] for grp in groups}
+    mom = {grp: tuple(torch.from_numpy(a.copy()).to(dev) for a in pair) for grp, pair in mom_host.items()}
+    count = torch.tensor([N], dtype=torch.int64, device=dev)
+    mk = np.zeros(cap, np.uint8)
+    mk[:N] = mask[:N]
+    tmask = torch.from_numpy(mk).to(dev)
+    sidx = torch.full((cap,), -1, dtype=torch.int32, device=dev)
+    status = torch.full((1,), 99, dtype=torch.int32, device=dev)
+    nsplit = torch.full((1,), -1, dtype=torch.int64, device=dev)
+    igsp.long_axis_split_full(t["means"], t["log_scales"], t["quats"], t["opacity_logits"], count, tmask, sidx,
+                              status, mom, n_split=nsplit, features=t["features"])
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in t.items()}
+    res.update(count=int(count.item()), status=int(status.item()), K=int(nsplit.item()),
+               split_idx=sidx.cpu().numpy(), host=host, mask=mk)
+    after = {grp: [a.cpu().numpy() for a in pair] for grp, pair in mom.items()}
+    return res, mom_host, after
+
+
+@pytest.mark.parametrize("N,K,F,groups", [
+    (3000, 700, 48, ("means", "log_scales", "quats", "opacity_logits", "features")),
+    (70001, 9000, 48, ("means", "opacity_logits", "features")),
+    (2049, 2049, 3, ("log_scales", "features")),
+    (5000, 0, 48, ("means", "features")),
+])
+def test_full_record_split(N, K, F, groups):
+    g = synth.gaussians(21, N)
+    mk = synth.mask(22, N, K)
+    cap = N + K + 77
+    res, before, after = _run_full(g, N, mk, cap, F, 23, groups)
+    ref = compare(res, N, cap, feats=res["host"]["features"])
+    for grp in groups:
+        for k in range(2):
+            want = oracle.las_moments(N, ref["split_idx"], {"x": before[grp][k]})["x"]
+            assert (after[grp][k] == want).all(), (grp, k)
+    # canary rows past N + K keep the parameters' canary and their moments
+    assert (res["features"][N + K:] == CANARY).all()
+
+
+def test_full_record_split_capacity_overflow_touches_nothing():
+    N, K, F = 4000, 400, 48
+    g = synth.gaussians(24, N)
+    mk = synth.mask(25, N, K)
+    cap = N + K - 1
+    res, before, after = _run_full(g, N, mk, cap, F, 26, ("means", "features"))
+    assert res["status"] == -6 and res["count"] == N
+    for grp in ("means", "features"):
+        for k in range(2):
+            assert (after[grp][k] == before[grp][k]).all()
+    assert (res["features"] == res["host"]["features"]).all()

@@ -167,3 +167,16 @@ def test_capacity_boundary_exact():
     short = oracle.las(N, g.means[:N + 9], g.log_scales[:N + 9], g.quats[:N + 9],
                        g.opacity_logits[:N + 9], mk)
     assert short["status"] == -6 and short["count"] == N      # one row short: nothing split
+
+
+def test_moments_reading_worked_example():
+    """Hand-worked: N = 4, rows 0 and 2 selected, capacity 7. Rows 0, 2 (the
+    first children) and 4, 5 (the second children) are cleared; rows 1, 3
+    (not split) and 6 (past N + K) keep their values."""
+    m = np.arange(1.0, 22.0).reshape(7, 3)
+    out = oracle.las_moments(4, [0, 2], {"m": m})["m"]
+    expect = m.copy()
+    expect[[0, 2, 4, 5]] = 0.0
+    assert (out == expect).all()
+    assert (out[[1, 3, 6]] == [[4, 5, 6], [10, 11, 12], [19, 20, 21]]).all()
+    assert (m == np.arange(1.0, 22.0).reshape(7, 3)).all()   # input untouched
