@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--wg-waves", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-view FP32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-select", action="store_true",
+                    help="skip the split-mask generation (edge scores onto Gaussians, threshold, budget)")
     ap.add_argument("--no-las-full", action="store_true",
                     help="skip the full-record split (48 features + Adam moments)")
     ap.add_argument("--no-unfused", action="store_true",
@@ -338,6 +340,34 @@ def main():
     fused_bytes = vb.pixels * per_px
     achieved = fused_bytes / (stage_ms["fused"] * 1e-3) / 1e9
     log(f"stages: {stage_ms}, las {las_ms}")
+
+    # ---- which Gaussians to split: edge scores of this step's maps moved onto
+    #      the Gaussians through synthetic pixel contributions, then the
+    #      gradient threshold and the budget (N, K of the same workload)
+    select = None
+    if has_las and not args.no_select:
+        t1 = time.time()
+        cb = synth.contributions(7000001 * w.index + 2, N0, vb.widths, vb.heights, 3)
+        gr = synth.grad_accum(7000001 * w.index + 3, N0)
+        thr = float(np.quantile(gr, 0.6))          # 40% of the Gaussians pass the gradient test
+        log(f"contributions: {cb.n} entries ({time.time() - t1:.1f}s)")
+        T = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+        cg, cv, cp, cw, tg = T(cb.gauss), T(cb.view), T(cb.pixel), T(cb.weight), T(gr)
+        smask = torch.zeros(N0, dtype=torch.uint8, device=dev)
+        sscore = torch.zeros(N0, dtype=torch.int64, device=dev)
+        scount = torch.tensor([N0], dtype=torch.int64, device=dev)
+        snsel = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def run_select():
+            igsp.split_mask(out, views, cg, cv, cp, cw, tg, scount, smask, sscore, grad_threshold=thr,
+                            budget=N0 + K, n_selected=snsel, stream=stream)
+        sms, _ = timed(run_select, 1, 5)
+        sbytes = 28 * cb.n + 133 * N0
+        select = {"contributions": cb.n, "gaussians": N0, "selected": int(snsel.item()), "ms": round(sms, 4),
+                  "contributions_per_s": round(cb.n / (sms * 1e-3), 1),
+                  "algorithmic_bytes": int(sbytes), "algorithmic_GBps": round(sbytes / (sms * 1e-3) / 1e9, 1)}
+        log(f"split mask: {sms:.3f} ms, {select['selected']} selected")
+        del cg, cv, cp, cw, tg, cb
 
     # ---- the full-record split a trainer calls: 48 feature floats per row
     #      and both Adam moments of every parameter group (same N, K, mask)
@@ -503,6 +533,8 @@ def main():
         las_bytes = N0 + 120 * K
         res["las"] = {"ms": round(las_ms, 4), "gaussians_split_per_s": round(K / (las_ms * 1e-3), 1),
                       "algorithmic_GBps": round(las_bytes / (las_ms * 1e-3) / 1e9, 1)}
+    if select:
+        res["split_mask"] = select
     if las_full:
         res["las_full_record"] = las_full
     if unfused:

@@ -246,6 +246,57 @@ igsp_status long_axis_split_full(const igsp_gaussians* g, const igsp_adam_moment
                                  const igsp_las_out* out, const igsp_las_params* params, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Which Gaussians to split (the selection that feeds Long-Axis-Split)      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Pixel contributions of Gaussians, as a rasteriser's backward pass knows
+ * them: entry c says Gaussian gauss[c] covers pixel pixel[c] (y * width + x)
+ * of view view[c] with blending weight weight[c]. Any order. (device)
+ */
+typedef struct {
+  const int32_t* gauss;
+  const int32_t* view;
+  const int32_t* pixel;
+  const float* weight;
+  int64_t n;               /* entries, >= 0 */
+} igsp_contributions;
+
+typedef struct {
+  float grad_threshold;    /* candidate iff grad[g] >= grad_threshold ...     */
+  int32_t warmup;          /* ... unless warmup != 0: every live Gaussian     */
+  int64_t budget;          /* Gaussians allowed after the split               */
+} igsp_select_params;
+
+/*
+ * Split mask from edge scores (Sec. 2.1's maps moved onto the Gaussians,
+ * Sec. 3's gradient threshold and warm-up, and a Gaussian budget). The paper
+ * names these parts without giving formulas; the readings taken are:
+ *   score[g] = sum over g's contributions of E_view[pixel] * weight, each
+ *              product in float32, accumulated exactly in int64 units of
+ *              2^-32 (floor of each product x 2^32; non-positive products
+ *              add nothing), so the sum does not depend on order;
+ *   candidates: live g (g < N = *count) with warmup or grad[g] >= threshold;
+ *   K = min(candidates, max(0, budget - N)) candidates with the largest
+ *   scores are selected, ties by lower index.
+ * maps     (device) float32 edge maps as edge_importance writes them, laid
+ *          out by `views` (only out_offset, width and height are read).
+ * views    (host) [n_views].
+ * contrib  (host struct, device arrays); entries naming a Gaussian >= N, a
+ *          view outside [0, n_views) or a pixel outside its view are ignored.
+ * grad     (device) float32 [capacity], rows [0, N) read.
+ * count    (device) int64 scalar N (not changed).
+ * mask     (device, out) uint8 [capacity]: rows [0, N) get 1 (selected) or 0.
+ * scores   (device, out) int64 [capacity]: rows [0, N) get the scores.
+ * n_selected (device, out, optional) int64 scalar K.
+ * Captures as kernel launches only (after a first call has built the plan).
+ */
+igsp_status split_mask(const float* maps, const igsp_view* views, int32_t n_views,
+                       const igsp_contributions* contrib, const float* grad, const int64_t* count,
+                       int64_t capacity, const igsp_select_params* params, uint8_t* mask, int64_t* scores,
+                       int64_t* n_selected, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* One densification step as a HIP graph                                    */
 /* ------------------------------------------------------------------------ */
 

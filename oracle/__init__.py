@@ -131,6 +131,57 @@ def opacity_update(o: float, beta: float = BETA) -> float:
     return float(lib().orc_opacity(float(o), float(beta)))
 
 
+def split_scores(maps, widths, heights, out_offset, gauss, view, pixel, weight, N: int) -> np.ndarray:
+    """Edge scores of Gaussians [0, N) (int64, units of 2^-32).
+
+    The paper moves its edge maps onto the Gaussians without a formula; the
+    reading taken: a Gaussian's score is the sum over its pixel contributions
+    of E_view[pixel] * weight, each product rounded to float32, then floor of
+    the product times 2^32 (exact), summed exactly as integers. Entries naming
+    a Gaussian >= N, an unknown view or a pixel outside its view add nothing,
+    nor do non-positive products.
+    """
+    maps = np.asarray(maps, np.float32)
+    W = np.asarray(widths, np.int64)
+    H = np.asarray(heights, np.int64)
+    off = np.asarray(out_offset, np.int64)
+    g = np.asarray(gauss, np.int64)
+    v = np.asarray(view, np.int64)
+    p = np.asarray(pixel, np.int64)
+    w = np.asarray(weight, np.float32)
+    ok = (g >= 0) & (g < N) & (v >= 0) & (v < W.size)
+    vv = np.where(ok, v, 0)
+    ok &= (p >= 0) & (p < W[vv] * H[vv])
+    e = np.zeros(g.size, np.float32)
+    e[ok] = maps[off[vv[ok]] + p[ok]] * w[ok]              # float32 products
+    ok &= e > 0
+    q = np.floor(e[ok].astype(np.float64) * 2.0 ** 32).astype(np.int64)
+    gs = g[ok]
+    scores = np.zeros(N, np.int64)
+    if gs.size:
+        order = np.argsort(gs, kind="stable")
+        gs, q = gs[order], q[order]
+        starts = np.flatnonzero(np.r_[True, gs[1:] != gs[:-1]])
+        scores[gs[starts]] = np.add.reduceat(q, starts)      # exact int64 sums
+    return scores
+
+
+def split_select(scores, grad, N: int, grad_threshold: float, warmup: bool, budget: int):
+    """Split mask over [0, N): candidates are Gaussians with grad >= threshold
+    (float32 compare), or all of them during warm-up; the K = min(candidates,
+    max(0, budget - N)) candidates of largest score are selected, ties by
+    lower index. Returns (mask uint8 [N], K)."""
+    grad = np.asarray(grad, np.float32)[:N]
+    cand = np.ones(N, bool) if warmup else grad >= np.float32(grad_threshold)
+    K = int(min(int(cand.sum()), max(0, int(budget) - N)))
+    idx = np.flatnonzero(cand)
+    sc = np.asarray(scores, np.int64)[idx]
+    order = np.lexsort((idx, -sc))                           # score descending, index ascending
+    mask = np.zeros(N, np.uint8)
+    mask[idx[order[:K]]] = 1
+    return mask, K
+
+
 def las_moments(N: int, split_idx, moments: dict) -> dict:
     """Optimiser state after the full-record split (FP64 copies).
 

@@ -25,8 +25,8 @@ STATUS = {
 }
 
 # Every symbol include/igsp.h declares.
-EXPORTS = ("edge_importance", "long_axis_split", "long_axis_split_full", "igsp_edge_autotune", "igsp_edge_resolve",
-           "igsp_step_create",
+EXPORTS = ("edge_importance", "long_axis_split", "long_axis_split_full", "split_mask", "igsp_edge_autotune",
+           "igsp_edge_resolve", "igsp_step_create",
            "igsp_step_launch", "igsp_step_destroy", "igsp_status_string", "igsp_release_plans", "igsp_version")
 
 # Tile shapes and launch forms the autotuner picked on MI355X for the
@@ -64,6 +64,15 @@ class LasParams(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_float), ("gamma", ctypes.c_float), ("beta", ctypes.c_float)]
 
 
+class Contributions(ctypes.Structure):
+    _fields_ = [("gauss", ctypes.c_void_p), ("view", ctypes.c_void_p), ("pixel", ctypes.c_void_p),
+                ("weight", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class SelectParams(ctypes.Structure):
+    _fields_ = [("grad_threshold", ctypes.c_float), ("warmup", ctypes.c_int32), ("budget", ctypes.c_int64)]
+
+
 class AdamMoments(ctypes.Structure):
     _fields_ = [(g, ctypes.c_void_p * 2) for g in ("means", "log_scales", "quats", "opacity_logits", "features")]
 
@@ -96,6 +105,9 @@ def lib():
         L.long_axis_split_full.argtypes = [ctypes.POINTER(Gaussians), ctypes.POINTER(AdamMoments), vp,
                                            ctypes.POINTER(LasOut), ctypes.POINTER(LasParams), vp]
         L.long_axis_split_full.restype = i32
+        L.split_mask.argtypes = [vp, ctypes.POINTER(View), i32, ctypes.POINTER(Contributions), vp, vp,
+                                 ctypes.c_int64, ctypes.POINTER(SelectParams), vp, vp, vp, vp]
+        L.split_mask.restype = i32
         L.igsp_edge_autotune.argtypes = [vp, ctypes.POINTER(View), i32, vp, i32, i32, ctypes.POINTER(EdgeOpts), vp]
         L.igsp_edge_autotune.restype = i32
         L.igsp_edge_resolve.argtypes = [ctypes.POINTER(View), i32, ctypes.POINTER(EdgeOpts)]
@@ -344,6 +356,38 @@ def long_axis_split_full(means, log_scales, quats, opacity_logits, count, mask, 
     prm = las_params(alpha, gamma, beta)
     _check(lib().long_axis_split_full(ctypes.byref(g), ctypes.byref(adam), _ptr(mask), ctypes.byref(out),
                                       ctypes.byref(prm), _stream(stream)), "long_axis_split_full")
+
+
+def split_mask(maps, views, gauss, view, pixel, weight, grad, count, mask, scores, grad_threshold=0.0,
+               warmup=False, budget=None, n_selected=None, stream=None):
+    """Split mask from edge scores into ``mask`` (uint8) and ``scores`` (int64,
+    units of 2^-32); N = count[0] on the device; budget None = capacity."""
+    import torch
+
+    _need(maps, torch.float32, "maps")
+    for t, dt, nm in ((gauss, torch.int32, "gauss"), (view, torch.int32, "view"), (pixel, torch.int32, "pixel"),
+                      (weight, torch.float32, "weight"), (grad, torch.float32, "grad"), (count, torch.int64, "count"),
+                      (mask, torch.uint8, "mask"), (scores, torch.int64, "scores")):
+        if t is None:
+            raise ValueError(f"{nm} is required")
+        _need(t, dt, nm)
+    _need(n_selected, torch.int64, "n_selected")
+    n = int(gauss.numel())
+    if not (view.numel() == pixel.numel() == weight.numel() == n):
+        raise ValueError("gauss, view, pixel and weight need the same length")
+    cap = int(mask.numel())
+    if grad.numel() < cap or scores.numel() < cap:
+        raise ValueError("grad and scores need capacity entries")
+    tab, nv = view_table(*views)
+    if nv:
+        out_end = max(tab[v].out_offset + tab[v].width * tab[v].height for v in range(nv))
+        if out_end > maps.numel():
+            raise ValueError(f"views need {out_end} map floats, the tensor has {maps.numel()}")
+    c = Contributions(_ptr(gauss), _ptr(view), _ptr(pixel), _ptr(weight), n)
+    prm = SelectParams(float(grad_threshold), int(bool(warmup)), cap if budget is None else int(budget))
+    _check(lib().split_mask(_ptr(maps), tab, nv, ctypes.byref(c), _ptr(grad), _ptr(count), cap,
+                            ctypes.byref(prm), _ptr(mask), _ptr(scores), _ptr(n_selected), _stream(stream)),
+           "split_mask")
 
 
 class Step:

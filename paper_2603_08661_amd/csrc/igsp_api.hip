@@ -531,10 +531,101 @@ igsp_status enqueue_las(LasPlan* P, const igsp_gaussians* g, const igsp_adam_mom
   return launch_las(L, s) == hipSuccess ? IGSP_OK : IGSP_ERR_HIP;
 }
 
+// ------------------------------------------------------------------ split mask
+
+struct SelPlan {
+  int device = 0;
+  int64_t capacity = 0;
+  std::vector<igsp_view> views;
+  SelView* d_views = nullptr;
+  uint32_t* d_hist = nullptr;
+  uint32_t* d_counts = nullptr;
+  int64_t* d_offsets = nullptr;
+  SelState* d_state = nullptr;
+  ~SelPlan() {
+    (void)hipFree(d_views); (void)hipFree(d_hist); (void)hipFree(d_counts); (void)hipFree(d_offsets);
+    (void)hipFree(d_state);
+  }
+};
+std::list<std::shared_ptr<SelPlan>> g_sel_plans;
+
+igsp_status get_sel_plan(const igsp_view* views, int32_t n_views, int64_t capacity,
+                         std::shared_ptr<SelPlan>* out) {
+  int dev = 0;
+  igsp_status st = check_device(&dev);
+  if (st != IGSP_OK) return st;
+  for (auto it = g_sel_plans.begin(); it != g_sel_plans.end(); ++it) {
+    const SelPlan& p = **it;
+    if (p.device == dev && p.capacity == capacity && (int32_t)p.views.size() == n_views &&
+        (n_views == 0 || std::memcmp(p.views.data(), views, n_views * sizeof(igsp_view)) == 0)) {
+      g_sel_plans.splice(g_sel_plans.begin(), g_sel_plans, it);
+      *out = g_sel_plans.front();
+      return IGSP_OK;
+    }
+  }
+  auto plan = std::make_shared<SelPlan>();
+  plan->device = dev;
+  plan->capacity = capacity;
+  plan->views.assign(views, views + n_views);
+  std::vector<SelView> sv(n_views);
+  for (int v = 0; v < n_views; ++v) sv[v] = SelView{views[v].out_offset, (int64_t)views[v].width * views[v].height};
+  const int64_t tiles = std::max<int64_t>(1, (capacity + kSelTile - 1) / kSelTile);
+  if (upload(&plan->d_views, sv) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_hist), 256 * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_counts), tiles * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_offsets), tiles * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_state), sizeof(SelState)) != hipSuccess)
+    return IGSP_ERR_HIP;
+  // the radix histogram starts at zero once; every pass clears what it read
+  if (hipMemset(plan->d_hist, 0, 256 * sizeof(uint32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return IGSP_ERR_HIP;
+  g_sel_plans.push_front(std::move(plan));
+  while ((int)g_sel_plans.size() > kMaxPlans) g_sel_plans.pop_back();
+  *out = g_sel_plans.front();
+  return IGSP_OK;
+}
+
 }  // namespace
 }  // namespace igsp
 
 using namespace igsp;
+
+extern "C" igsp_status split_mask(const float* maps, const igsp_view* views, int32_t n_views,
+                                  const igsp_contributions* contrib, const float* grad, const int64_t* count,
+                                  int64_t capacity, const igsp_select_params* params, uint8_t* mask,
+                                  int64_t* scores, int64_t* n_selected, void* stream) {
+  igsp_status st = validate_select(maps, views, n_views, contrib, grad, count, capacity, params, mask, scores);
+  if (st != IGSP_OK) return st;
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::shared_ptr<SelPlan> plan;
+  st = get_sel_plan(views, n_views, capacity, &plan);
+  if (st != IGSP_OK) return st;
+  SelLaunch S{};
+  S.maps = maps;
+  S.views = plan->d_views;
+  S.n_views = n_views;
+  S.gauss = contrib->gauss;
+  S.view = contrib->view;
+  S.pixel = contrib->pixel;
+  S.weight = contrib->weight;
+  S.n_contrib = contrib->n;
+  S.grad = grad;
+  S.count = count;
+  S.capacity = capacity;
+  S.grad_threshold = params->grad_threshold;
+  S.warmup = params->warmup;
+  S.budget = params->budget;
+  S.mask = mask;
+  S.scores = scores;
+  S.n_selected = n_selected;
+  S.hist = plan->d_hist;
+  S.tile_counts = plan->d_counts;
+  S.tile_offsets = plan->d_offsets;
+  S.state = plan->d_state;
+  const int64_t tiles = std::max<int64_t>(1, (capacity + kSelTile - 1) / kSelTile);
+  S.grid = (int)std::min<int64_t>(tiles, kSelGrid);
+  return launch_select(S, static_cast<hipStream_t>(stream)) == hipSuccess ? IGSP_OK : IGSP_ERR_HIP;
+}
 
 extern "C" int32_t igsp_version(void) { return 1; }
 
@@ -734,4 +825,5 @@ extern "C" void igsp_release_plans(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_edge_plans.clear();
   g_las_plans.clear();
+  g_sel_plans.clear();
 }

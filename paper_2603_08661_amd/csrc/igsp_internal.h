@@ -189,4 +189,55 @@ struct LasLaunch {
 
 hipError_t launch_las(const LasLaunch& L, hipStream_t s);
 
+// ---------------------------------------------------------------- split mask
+
+constexpr int kSelThreads = 256;
+constexpr int kSelTile = 2048;         // rows per tile of the count / mask kernels
+constexpr int kSelGrid = 1024;         // work-groups of the grid-stride kernels
+constexpr int kSelScatterGrid = 8192;  // work-groups of the contribution scatter
+
+struct SelView {
+  int64_t out_offset;  // floats from `maps`
+  int64_t pixels;      // width * height
+};
+
+struct SelState {      // device scalars of one selection
+  uint64_t prefix;     // resolved high bits of the K-th largest key
+  uint64_t kth;        // the K-th largest key (valid once shift == 0)
+  int64_t rank;        // rank inside the prefix group, from the top; at the
+                       // end: the ties at kth still to take
+  int64_t k;           // Gaussians to select
+  int64_t candidates;
+  int64_t ties;
+  int32_t shift;       // low bits still unresolved
+  int32_t pad;
+};
+
+struct SelLaunch {
+  const float* maps;
+  const SelView* views;
+  int32_t n_views;
+  const int32_t* gauss;
+  const int32_t* view;
+  const int32_t* pixel;
+  const float* weight;
+  int64_t n_contrib;
+  const float* grad;
+  const int64_t* count;
+  int64_t capacity;
+  float grad_threshold;
+  int32_t warmup;
+  int64_t budget;
+  uint8_t* mask;
+  int64_t* scores;
+  int64_t* n_selected;
+  uint32_t* hist;           // [256], zero between passes
+  uint32_t* tile_counts;    // [tiles]
+  int64_t* tile_offsets;    // [tiles]
+  SelState* state;
+  int grid;
+};
+
+hipError_t launch_select(const SelLaunch& S, hipStream_t s);
+
 }  // namespace igsp

@@ -1,0 +1,237 @@
+// Split-mask generation on gfx950: which Gaussians the next Long-Axis-Split
+// takes (the selection that feeds it; Sec. 2.1's edge scores moved to the
+// Gaussians, Sec. 3's gradient threshold and warm-up, and a budget).
+//
+//   sel_clear   : scores[0, N) = 0 (a fill kernel, so the call can be captured)
+//   sel_scatter : per contribution (Gaussian g, view v, pixel p, weight w):
+//                 scores[g] += floor(fl32(E_v[p] * w) * 2^32) with 64-bit
+//                 atomics; fixed point makes the sum exact and independent
+//                 of the order the atomics land in
+//   sel_count   : candidates (warm-up, or grad[g] >= threshold) per tile
+//   sel_start   : K = min(candidates, max(0, budget - N)) and the first
+//                 radix digit
+//   sel_hist / sel_pick : exact radix selection, 8 bits at a time from the
+//                 top, of the K-th largest key, key = score + 1 for a
+//                 candidate and 0 otherwise
+//   sel_ties / sel_tie_scan / sel_mask : ties at the K-th key are taken in
+//                 ascending index order (per-tile counts, one scan, write)
+#include "igsp_internal.h"
+
+namespace igsp {
+namespace {
+
+__device__ __forceinline__ int64_t live_count(const SelLaunch& S) {
+  const int64_t n = *S.count;
+  return n < 0 ? 0 : (n > S.capacity ? S.capacity : n);
+}
+
+__device__ __forceinline__ bool candidate(const SelLaunch& S, int64_t g) {
+  return S.warmup || S.grad[g] >= S.grad_threshold;
+}
+
+__device__ __forceinline__ uint64_t key_of(const SelLaunch& S, int64_t g) {
+  return candidate(S, g) ? (uint64_t)S.scores[g] + 1ull : 0ull;
+}
+
+__global__ __launch_bounds__(kSelThreads) void sel_clear_kernel(SelLaunch S) {
+  const int64_t N = live_count(S);
+  for (int64_t g = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; g < N; g += (int64_t)gridDim.x * kSelThreads)
+    S.scores[g] = 0;
+}
+
+__global__ __launch_bounds__(kSelThreads) void sel_scatter_kernel(SelLaunch S) {
+  const int64_t N = live_count(S);
+  for (int64_t c = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; c < S.n_contrib;
+       c += (int64_t)gridDim.x * kSelThreads) {
+    const int32_t g = S.gauss[c], v = S.view[c], p = S.pixel[c];
+    if (g < 0 || g >= N || v < 0 || v >= S.n_views) continue;     // outside the live set: ignored
+    const SelView sv = S.views[v];
+    if (p < 0 || (int64_t)p >= sv.pixels) continue;
+    const float e = S.maps[sv.out_offset + p] * S.weight[c];       // one FP32 product
+    if (!(e > 0.0f)) continue;                                     // zero, negative or NaN adds nothing
+    const double f = floor((double)e * 4294967296.0);              // exact: fl32 times 2^32
+    atomicAdd(reinterpret_cast<unsigned long long*>(S.scores + g), (unsigned long long)f);
+  }
+}
+
+// Exclusive scan over the work-group (kSelThreads threads).
+__device__ __forceinline__ uint32_t sel_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kSelThreads / 64; ++k) {
+    const uint32_t t = wsum[k];
+    if (k < w) before += t;
+    tot += t;
+  }
+  total = tot;
+  __syncthreads();
+  return before + x - v;
+}
+
+// Per tile of kSelTile rows: candidates (mode 0) or keys equal to the
+// selected K-th key (mode 1).
+template <int MODE>
+__global__ __launch_bounds__(kSelThreads) void sel_count_kernel(SelLaunch S) {
+  __shared__ uint32_t wsum[kSelThreads / 64];
+  const int64_t N = live_count(S);
+  const int nt = (int)((N + kSelTile - 1) / kSelTile);
+  const uint64_t T = MODE == 1 ? S.state->kth : 0;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    uint32_t c = 0;
+    for (int k = 0; k < kSelTile / kSelThreads; ++k) {
+      const int64_t g = (int64_t)t * kSelTile + k * kSelThreads + threadIdx.x;
+      if (g < N) c += MODE == 0 ? (candidate(S, g) ? 1u : 0u) : (key_of(S, g) == T ? 1u : 0u);
+    }
+    uint32_t total = 0;
+    (void)sel_scan(c, wsum, total);
+    if (threadIdx.x == 0) S.tile_counts[t] = total;
+  }
+}
+
+// One work-group: exclusive scan of the tile counts; mode 0 derives K and
+// starts the selection, mode 1 turns the tie counts into tie ranks.
+template <int MODE>
+__global__ __launch_bounds__(1024) void sel_scan_kernel(SelLaunch S) {
+  __shared__ int64_t wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t N = live_count(S);
+  const int nt = (int)((N + kSelTile - 1) / kSelTile);
+  const int per = (nt + 1023) / 1024;
+  const int t0 = tid * per;
+  int64_t v = 0;
+  for (int k = 0; k < per; ++k)
+    if (t0 + k < nt) v += S.tile_counts[t0 + k];
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int64_t run = 0, total = 0;
+  for (int k = 0; k < 16; ++k) {
+    if (k < w) run += wsum[k];
+    total += wsum[k];
+  }
+  run += x - v;
+  for (int k = 0; k < per; ++k)
+    if (t0 + k < nt) {
+      S.tile_offsets[t0 + k] = run;
+      run += S.tile_counts[t0 + k];
+    }
+  if (tid == 0) {
+    SelState* st = S.state;
+    if (MODE == 0) {
+      const int64_t room = S.budget > N ? S.budget - N : 0;
+      const int64_t K = total < room ? total : room;
+      st->candidates = total;
+      st->k = K;
+      st->prefix = 0;
+      st->rank = K;          // the K-th largest key: K - 1 keys above it
+      st->shift = 64;
+      st->kth = 0;
+      if (S.n_selected) *S.n_selected = K;
+    } else {
+      st->ties = total;
+    }
+  }
+}
+
+// One radix pass: histogram of the next 8-bit digit of the keys whose
+// already-resolved high bits equal the prefix.
+__global__ __launch_bounds__(kSelThreads) void sel_hist_kernel(SelLaunch S) {
+  __shared__ uint32_t h[256];
+  const SelState st = *S.state;
+  if (st.k == 0 || st.shift == 0) return;  // nothing to select / resolved
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t N = live_count(S);
+  const int shift = st.shift - 8;
+  for (int64_t g = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; g < N; g += (int64_t)gridDim.x * kSelThreads) {
+    const uint64_t key = key_of(S, g);
+    if (st.shift == 64 || (key >> st.shift) == st.prefix) atomicAdd(&h[(key >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  const uint32_t c = h[threadIdx.x];
+  if (c) atomicAdd(&S.hist[threadIdx.x], c);
+}
+
+// Pick the digit holding the rank-th largest key among the prefix's keys.
+__global__ __launch_bounds__(256) void sel_pick_kernel(SelLaunch S) {
+  __shared__ uint32_t cnt[256];
+  SelState st = *S.state;
+  const uint32_t c = S.hist[threadIdx.x];
+  S.hist[threadIdx.x] = 0;  // ready for the next pass or call
+  if (st.k == 0 || st.shift == 0) return;
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t rank = st.rank;  // 1-based from the top
+    int d = 255;
+    for (; d > 0; --d) {
+      if ((int64_t)cnt[d] >= rank) break;
+      rank -= cnt[d];
+    }
+    st.prefix = (st.prefix << 8) | (uint64_t)d;
+    st.shift -= 8;
+    st.rank = rank;
+    if (st.shift == 0) st.kth = st.prefix;
+    *S.state = st;
+  }
+}
+
+__global__ __launch_bounds__(kSelThreads) void sel_mask_kernel(SelLaunch S) {
+  __shared__ uint32_t wsum[kSelThreads / 64];
+  const SelState st = *S.state;
+  const int64_t N = live_count(S);
+  const int nt = (int)((N + kSelTile - 1) / kSelTile);
+  // keys above the K-th key: K - rank of them; the remaining `need` come
+  // from the ties at the K-th key, lowest index first
+  const int64_t need = st.rank;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    int64_t before = st.k > 0 ? S.tile_offsets[t] : 0;
+    for (int k = 0; k < kSelTile / kSelThreads; ++k) {
+      const int64_t g = (int64_t)t * kSelTile + k * kSelThreads + threadIdx.x;
+      const uint64_t key = g < N ? key_of(S, g) : 0;
+      const bool tie = st.k > 0 && g < N && key == st.kth;
+      uint32_t total = 0;
+      const uint32_t r = sel_scan(tie ? 1u : 0u, wsum, total);
+      if (g < N) S.mask[g] = (uint8_t)(st.k > 0 && (key > st.kth || (tie && before + r < need)));
+      before += total;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_select(const SelLaunch& S, hipStream_t s) {
+  const int grid = S.grid;
+  hipLaunchKernelGGL(sel_clear_kernel, dim3(grid), dim3(kSelThreads), 0, s, S);
+  if (S.n_contrib > 0) {
+    const int64_t cg = (S.n_contrib + kSelThreads - 1) / kSelThreads;
+    hipLaunchKernelGGL(sel_scatter_kernel, dim3((unsigned)(cg < kSelScatterGrid ? cg : kSelScatterGrid)),
+                       dim3(kSelThreads), 0, s, S);
+  }
+  hipLaunchKernelGGL(sel_count_kernel<0>, dim3(grid), dim3(kSelThreads), 0, s, S);
+  hipLaunchKernelGGL(sel_scan_kernel<0>, dim3(1), dim3(1024), 0, s, S);
+  for (int pass = 0; pass < 8; ++pass) {
+    hipLaunchKernelGGL(sel_hist_kernel, dim3(grid), dim3(kSelThreads), 0, s, S);
+    hipLaunchKernelGGL(sel_pick_kernel, dim3(1), dim3(256), 0, s, S);
+  }
+  hipLaunchKernelGGL(sel_count_kernel<1>, dim3(grid), dim3(kSelThreads), 0, s, S);
+  hipLaunchKernelGGL(sel_scan_kernel<1>, dim3(1), dim3(1024), 0, s, S);
+  hipLaunchKernelGGL(sel_mask_kernel, dim3(grid), dim3(kSelThreads), 0, s, S);
+  return hipGetLastError();
+}
+
+}  // namespace igsp

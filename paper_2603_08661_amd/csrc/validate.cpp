@@ -62,6 +62,26 @@ igsp_status validate_las(const igsp_gaussians* g, const uint8_t* mask, const igs
   return IGSP_OK;
 }
 
+igsp_status validate_select(const float* maps, const igsp_view* views, int32_t n_views,
+                            const igsp_contributions* c, const float* grad, const int64_t* count,
+                            int64_t capacity, const igsp_select_params* p, const uint8_t* mask,
+                            const int64_t* scores) {
+  if (!c || !grad || !count || !p || !mask || !scores) return IGSP_ERR_NULL;
+  if (n_views < 0 || c->n < 0) return IGSP_ERR_DIMS;
+  if (capacity < 0 || capacity >= (int64_t(1) << 31)) return IGSP_ERR_DIMS;
+  if (c->n > 0 && (!c->gauss || !c->view || !c->pixel || !c->weight || !maps || (n_views > 0 && !views)))
+    return IGSP_ERR_NULL;
+  if (p->warmup != 0 && p->warmup != 1) return IGSP_ERR_PARAM;
+  if (p->budget < 0) return IGSP_ERR_PARAM;
+  if (std::isnan(p->grad_threshold)) return IGSP_ERR_PARAM;
+  for (int32_t v = 0; v < n_views; ++v) {
+    const igsp_view& d = views[v];
+    if (d.width < 0 || d.height < 0 || d.out_offset < 0) return IGSP_ERR_DIMS;
+    if ((int64_t)d.width * d.height >= (int64_t(1) << 31)) return IGSP_ERR_DIMS;
+  }
+  return IGSP_OK;
+}
+
 }  // namespace igsp
 
 extern "C" const char* igsp_status_string(int32_t status) {

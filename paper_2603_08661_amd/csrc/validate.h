@@ -15,6 +15,10 @@ struct EdgeExtent {
 
 igsp_status validate_edge(const uint8_t* images, const igsp_view* views, int32_t n_views, const float* out,
                           const igsp_edge_opts* opts, EdgeExtent* ext);
+igsp_status validate_select(const float* maps, const igsp_view* views, int32_t n_views,
+                            const igsp_contributions* c, const float* grad, const int64_t* count,
+                            int64_t capacity, const igsp_select_params* p, const uint8_t* mask,
+                            const int64_t* scores);
 igsp_status validate_las(const igsp_gaussians* g, const uint8_t* mask, const igsp_las_out* out,
                          const igsp_las_params* p);
 

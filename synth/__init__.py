@@ -50,8 +50,11 @@ def lib():
         L.syn_view_sizes.argtypes = [u64, i32, i32, i32, dbl, dbl, vp, vp]
         L.syn_gaussians.argtypes = [u64, i64, dbl, dbl, vp, vp, vp, vp]
         L.syn_mask.argtypes = [u64, i64, i64, vp]
+        L.syn_contrib_count.argtypes = [u64, i64, i32, vp, vp, i32, vp]
+        L.syn_contrib_count.restype = i64
+        L.syn_contrib_fill.argtypes = [u64, i64, i32, vp, vp, i32, vp, vp, vp, vp, vp]
         for f in ("syn_image", "syn_image_down2", "syn_image_batch", "syn_view_sizes",
-                  "syn_gaussians", "syn_mask"):
+                  "syn_gaussians", "syn_mask", "syn_contrib_fill"):
             getattr(L, f).restype = None
         _lib = L
     return _lib
@@ -187,6 +190,37 @@ def mask(seed: int, N: int, K: int) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 ASPECT_LO, ASPECT_HI = 1.5, 16.0 / 9.0
+
+
+@dataclass
+class Contributions:
+    """Pixel contributions (Gaussian, view, pixel = y * width + x, weight)."""
+    gauss: np.ndarray
+    view: np.ndarray
+    pixel: np.ndarray
+    weight: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.gauss.shape[0])
+
+
+def contributions(seed: int, n_gauss: int, widths, heights, mean_radius: int = 3) -> Contributions:
+    """Synthetic contributions of n_gauss Gaussians over views of the given
+    sizes (each Gaussian a clipped disc in one view; see synth.c)."""
+    W = np.ascontiguousarray(widths, np.int32)
+    H = np.ascontiguousarray(heights, np.int32)
+    off = np.zeros(n_gauss + 1, np.int64)
+    n = lib().syn_contrib_count(seed, n_gauss, int(W.size), _p(W), _p(H), int(mean_radius), _p(off))
+    c = Contributions(np.zeros(n, np.int32), np.zeros(n, np.int32), np.zeros(n, np.int32), np.zeros(n, np.float32))
+    lib().syn_contrib_fill(seed, n_gauss, int(W.size), _p(W), _p(H), int(mean_radius), _p(off), _p(c.gauss),
+                           _p(c.view), _p(c.pixel), _p(c.weight))
+    return c
+
+
+def grad_accum(seed: int, n: int) -> np.ndarray:
+    """Synthetic accumulated view-space gradient norms (log-normal, float32)."""
+    return np.random.default_rng(seed).lognormal(-9.0, 1.0, n).astype(np.float32)
 
 
 @dataclass

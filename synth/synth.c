@@ -285,3 +285,85 @@ void syn_mask(uint64_t seed, int64_t N, int64_t K, uint8_t* mask) {
   }
   free(idx);
 }
+
+/* ---------------------------------------------------------------- contributions
+ * Synthetic pixel contributions of Gaussians, standing in for what a
+ * rasteriser's backward pass knows: Gaussian g covers a disc of integer
+ * radius r in [1, 2 * mean_radius - 1] around a uniform centre of one uniform
+ * view, clipped to the view, with weight a * exp(-d^2 / (2 (r/2)^2)) for a
+ * per-Gaussian opacity a in [0.05, 1). Everything about Gaussian g is drawn
+ * from a generator keyed by (seed, g), so the lists of different Gaussians
+ * are independent of each other and of the thread count. Entries are then
+ * spread by the bijection i -> (i * P) mod n (P prime, not dividing n), so
+ * neighbouring entries belong to different Gaussians.
+ */
+typedef struct {
+  int32_t v, cx, cy, r;
+  double a;
+} foot_t;
+
+static foot_t footprint(uint64_t seed, int64_t g, int32_t n_views, const int32_t* W, const int32_t* H,
+                        int32_t mean_radius) {
+  rng_t rg = {mix64(seed * 0x9E3779B97F4A7C15ULL + (uint64_t)g)};
+  foot_t f;
+  f.v = (int32_t)rng_int(&rg, 0, n_views - 1);
+  f.cx = (int32_t)rng_int(&rg, 0, W[f.v] - 1);
+  f.cy = (int32_t)rng_int(&rg, 0, H[f.v] - 1);
+  f.r = (int32_t)rng_int(&rg, 1, 2 * mean_radius - 1);
+  f.a = rng_uniform(&rg, 0.05, 1.0);
+  return f;
+}
+
+static int64_t foot_count(const foot_t* f, const int32_t* W, const int32_t* H) {
+  int64_t c = 0;
+  for (int dy = -f->r; dy <= f->r; ++dy)
+    for (int dx = -f->r; dx <= f->r; ++dx) {
+      const int x = f->cx + dx, y = f->cy + dy;
+      if (dx * dx + dy * dy <= f->r * f->r && x >= 0 && y >= 0 && x < W[f->v] && y < H[f->v]) ++c;
+    }
+  return c;
+}
+
+/* Number of entries for n_gauss Gaussians (first call), then the entries. */
+int64_t syn_contrib_count(uint64_t seed, int64_t n_gauss, int32_t n_views, const int32_t* W, const int32_t* H,
+                          int32_t mean_radius, int64_t* offsets /* [n_gauss + 1] */) {
+#pragma omp parallel for schedule(static)
+  for (int64_t g = 0; g < n_gauss; ++g) {
+    const foot_t f = footprint(seed, g, n_views, W, H, mean_radius);
+    offsets[g + 1] = foot_count(&f, W, H);
+  }
+  offsets[0] = 0;
+  for (int64_t g = 0; g < n_gauss; ++g) offsets[g + 1] += offsets[g];
+  return offsets[n_gauss];
+}
+
+static int64_t gcd64(int64_t a, int64_t b) {
+  while (b) { const int64_t t = a % b; a = b; b = t; }
+  return a;
+}
+
+void syn_contrib_fill(uint64_t seed, int64_t n_gauss, int32_t n_views, const int32_t* W, const int32_t* H,
+                      int32_t mean_radius, const int64_t* offsets, int32_t* gauss, int32_t* view, int32_t* pixel,
+                      float* weight) {
+  const int64_t n = offsets[n_gauss];
+  if (n == 0) return;
+  int64_t P = 1000003;  /* prime; step to the next prime-ish value until coprime with n */
+  while (gcd64(P, n) != 1) P += 2;
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t g = 0; g < n_gauss; ++g) {
+    const foot_t f = footprint(seed, g, n_views, W, H, mean_radius);
+    const double s2 = 2.0 * (0.5 * f.r) * (0.5 * f.r);
+    int64_t i = offsets[g];
+    for (int dy = -f.r; dy <= f.r; ++dy)
+      for (int dx = -f.r; dx <= f.r; ++dx) {
+        const int x = f.cx + dx, y = f.cy + dy;
+        if (dx * dx + dy * dy > f.r * f.r || x < 0 || y < 0 || x >= W[f.v] || y >= H[f.v]) continue;
+        const int64_t o = (int64_t)(((__int128)i * P) % n);
+        gauss[o] = (int32_t)g;
+        view[o] = f.v;
+        pixel[o] = y * W[f.v] + x;
+        weight[o] = (float)(f.a * exp(-(double)(dx * dx + dy * dy) / s2));
+        ++i;
+      }
+  }
+}

@@ -160,3 +160,25 @@ def test_tuning_table_lookup_and_override(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
                          check=True).stdout.strip()
     assert out.startswith("('staged', 48, 8)"), out
+
+
+def test_split_mask_validation():
+    L = igsp.lib()
+    good_c = B.Contributions(0x10, 0x20, 0x30, 0x40, 5)
+    prm = B.SelectParams(0.0, 0, 100)
+    arr = (B.View * 1)(B.View(4, 4, 0, 0))
+
+    def call(c=good_c, p=prm, cap=100, maps=0x50, grad=0x60, count=0x70, mask=0x80, scores=0x90, nv=1):
+        return L.split_mask(maps, arr, nv, ctypes.byref(c) if c else None, grad, count, cap,
+                            ctypes.byref(p) if p else None, mask, scores, None, None)
+
+    assert call(c=None) == -1 and call(p=None) == -1
+    assert call(grad=0) == -1 and call(count=0) == -1 and call(mask=0) == -1 and call(scores=0) == -1
+    assert call(maps=0) == -1                                     # entries but no maps
+    assert call(c=B.Contributions(0x10, 0, 0x30, 0x40, 5)) == -1
+    assert call(c=B.Contributions(0, 0, 0, 0, -1)) == -2
+    assert call(cap=-1) == -2 and call(cap=2 ** 31) == -2 and call(nv=-1) == -2
+    assert call(p=B.SelectParams(0.0, 2, 100)) == -5
+    assert call(p=B.SelectParams(0.0, 0, -1)) == -5
+    assert call(p=B.SelectParams(float("nan"), 0, 100)) == -5
+    assert ctypes.sizeof(B.Contributions) == 40 and ctypes.sizeof(B.SelectParams) == 16
