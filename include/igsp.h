@@ -297,6 +297,20 @@ igsp_status split_mask(const float* maps, const igsp_view* views, int32_t n_view
                        int64_t* n_selected, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Learning-rate schedules (Sec. 3)                                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Exponential schedule: lr(t) = lr_init * (lr_final / lr_init)^(s / t_max)
+ * with s = t clamped to [0, t_max]. The paper decays the scale learning rate
+ * from 0.020 to 0.002 (gamma = 0.1) and the position learning rate from
+ * 0.000128 to 0.0000128; the iteration span it decays over is not stated, the
+ * caller passes it (t_max). Host function, no GPU work.
+ * Returns NaN if lr_init or lr_final is not positive or t_max < 1.
+ */
+double igsp_lr_exponential(int64_t t, double lr_init, double lr_final, int64_t t_max);
+
+/* ------------------------------------------------------------------------ */
 /* One densification step as a HIP graph                                    */
 /* ------------------------------------------------------------------------ */
 

@@ -17,6 +17,8 @@ import ctypes
 import os
 import subprocess
 
+import math
+
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -234,3 +236,12 @@ def las(N: int, means, log_scales, quats, opacity_logits, mask, feats=None,
     if F == 0:
         out["feats"] = out["feats"][:, :0]
     return out
+
+
+def lr_exponential(t: int, lr_init: float, lr_final: float, t_max: int) -> float:
+    """Exponential learning-rate schedule (Sec. 3): log-linear interpolation
+    from lr_init at t = 0 to lr_final at t = t_max, constant outside."""
+    if not (lr_init > 0 and lr_final > 0 and t_max >= 1):
+        return math.nan
+    s = min(max(t, 0), t_max) / t_max
+    return lr_init * (lr_final / lr_init) ** s

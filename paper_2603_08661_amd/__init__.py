@@ -13,6 +13,6 @@ plus ``Step``, one densification step recorded as a HIP graph.
 """
 from ._binding import (  # noqa: F401
     BATCHED, BATCHED_PERSISTENT, BATCHED_STAGED, BF16, EXPORTS, FORMS, FP16, FP32, LIB_PATH, PLAIN, PRECISIONS,
-    IgspError, Step, edge_autotune, edge_importance, edge_resolve, form_code, lib, long_axis_split, long_axis_split_full, release_plans, split_mask, status_string,
+    IgspError, Step, edge_autotune, edge_importance, edge_resolve, form_code, lib, long_axis_split, long_axis_split_full, lr_exponential, release_plans, split_mask, status_string,
     view_table,
 )

@@ -27,7 +27,8 @@ STATUS = {
 # Every symbol include/igsp.h declares.
 EXPORTS = ("edge_importance", "long_axis_split", "long_axis_split_full", "split_mask", "igsp_edge_autotune",
            "igsp_edge_resolve", "igsp_step_create",
-           "igsp_step_launch", "igsp_step_destroy", "igsp_status_string", "igsp_release_plans", "igsp_version")
+           "igsp_step_launch", "igsp_step_destroy", "igsp_status_string", "igsp_release_plans", "igsp_version",
+           "igsp_lr_exponential")
 
 # Tile shapes and launch forms the autotuner picked on MI355X for the
 # benchmark geometries; the library reads this table unless the caller's
@@ -122,6 +123,8 @@ def lib():
         L.igsp_step_destroy.restype = None
         L.igsp_status_string.argtypes = [i32]
         L.igsp_status_string.restype = ctypes.c_char_p
+        L.igsp_lr_exponential.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_int64]
+        L.igsp_lr_exponential.restype = ctypes.c_double
         L.igsp_release_plans.argtypes = []
         L.igsp_release_plans.restype = None
         L.igsp_version.argtypes = []
@@ -432,6 +435,11 @@ class Step:
             self.close()
         except Exception:
             pass
+
+
+def lr_exponential(t: int, lr_init: float, lr_final: float, t_max: int) -> float:
+    """Exponential learning-rate schedule (host): lr_init -> lr_final over t_max."""
+    return float(lib().igsp_lr_exponential(int(t), float(lr_init), float(lr_final), int(t_max)))
 
 
 def release_plans():

@@ -84,6 +84,12 @@ igsp_status validate_select(const float* maps, const igsp_view* views, int32_t n
 
 }  // namespace igsp
 
+extern "C" double igsp_lr_exponential(int64_t t, double lr_init, double lr_final, int64_t t_max) {
+  if (!(lr_init > 0.0) || !(lr_final > 0.0) || t_max < 1) return std::nan("");
+  const double s = t < 0 ? 0.0 : (t > t_max ? 1.0 : (double)t / (double)t_max);
+  return std::exp((1.0 - s) * std::log(lr_init) + s * std::log(lr_final));
+}
+
 extern "C" const char* igsp_status_string(int32_t status) {
   switch (status) {
     case IGSP_OK: return "ok";
