@@ -200,6 +200,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-select", action="store_true",
                     help="skip the split-mask generation (edge scores onto Gaussians, threshold, budget)")
+    ap.add_argument("--contrib-order", default="rows", choices=["rows", "spread"],
+                    help="order of the synthetic pixel contributions of the split-mask line")
     ap.add_argument("--no-las-full", action="store_true",
                     help="skip the full-record split (48 features + Adam moments)")
     ap.add_argument("--no-unfused", action="store_true",
@@ -347,7 +349,7 @@ def main():
     select = None
     if has_las and not args.no_select:
         t1 = time.time()
-        cb = synth.contributions(7000001 * w.index + 2, N0, vb.widths, vb.heights, 3)
+        cb = synth.contributions(7000001 * w.index + 2, N0, vb.widths, vb.heights, 3, order=args.contrib_order)
         gr = synth.grad_accum(7000001 * w.index + 3, N0)
         thr = float(np.quantile(gr, 0.6))          # 40% of the Gaussians pass the gradient test
         log(f"contributions: {cb.n} entries ({time.time() - t1:.1f}s)")
@@ -363,7 +365,8 @@ def main():
                             budget=N0 + K, n_selected=snsel, stream=stream)
         sms, _ = timed(run_select, 1, 5)
         sbytes = 28 * cb.n + 133 * N0
-        select = {"contributions": cb.n, "gaussians": N0, "selected": int(snsel.item()), "ms": round(sms, 4),
+        select = {"contributions": cb.n, "order": args.contrib_order, "gaussians": N0,
+                  "selected": int(snsel.item()), "ms": round(sms, 4),
                   "contributions_per_s": round(cb.n / (sms * 1e-3), 1),
                   "algorithmic_bytes": int(sbytes), "algorithmic_GBps": round(sbytes / (sms * 1e-3) / 1e9, 1)}
         log(f"split mask: {sms:.3f} ms, {select['selected']} selected")

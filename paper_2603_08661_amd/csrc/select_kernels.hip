@@ -4,9 +4,10 @@
 //
 //   sel_clear   : scores[0, N) = 0 (a fill kernel, so the call can be captured)
 //   sel_scatter : per contribution (Gaussian g, view v, pixel p, weight w):
-//                 scores[g] += floor(fl32(E_v[p] * w) * 2^32) with 64-bit
-//                 atomics; fixed point makes the sum exact and independent
-//                 of the order the atomics land in
+//                 scores[g] += floor(fl32(E_v[p] * w) * 2^32), runs of equal
+//                 g on consecutive lanes summed first, then 64-bit atomics;
+//                 fixed point makes the sum exact and independent of the
+//                 order the additions land in
 //   sel_count   : candidates (warm-up, or grad[g] >= threshold) per tile
 //   sel_start   : K = min(candidates, max(0, budget - N)) and the first
 //                 radix digit
@@ -39,18 +40,39 @@ __global__ __launch_bounds__(kSelThreads) void sel_clear_kernel(SelLaunch S) {
     S.scores[g] = 0;
 }
 
+// Contributions arrive in image order, so neighbouring entries often name the
+// same Gaussian: each wavefront first sums the runs of equal Gaussian index on
+// consecutive lanes (a segmented suffix sum over the lanes), and only a run's
+// first lane issues the 64-bit atomic.
 __global__ __launch_bounds__(kSelThreads) void sel_scatter_kernel(SelLaunch S) {
   const int64_t N = live_count(S);
-  for (int64_t c = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; c < S.n_contrib;
-       c += (int64_t)gridDim.x * kSelThreads) {
-    const int32_t g = S.gauss[c], v = S.view[c], p = S.pixel[c];
-    if (g < 0 || g >= N || v < 0 || v >= S.n_views) continue;     // outside the live set: ignored
-    const SelView sv = S.views[v];
-    if (p < 0 || (int64_t)p >= sv.pixels) continue;
-    const float e = S.maps[sv.out_offset + p] * S.weight[c];       // one FP32 product
-    if (!(e > 0.0f)) continue;                                     // zero, negative or NaN adds nothing
-    const double f = floor((double)e * 4294967296.0);              // exact: fl32 times 2^32
-    atomicAdd(reinterpret_cast<unsigned long long*>(S.scores + g), (unsigned long long)f);
+  const int lane = threadIdx.x & 63;
+  for (int64_t c0 = (int64_t)blockIdx.x * kSelThreads; c0 < S.n_contrib; c0 += (int64_t)gridDim.x * kSelThreads) {
+    const int64_t c = c0 + threadIdx.x;
+    int32_t g = -1;
+    uint64_t q = 0;
+    if (c < S.n_contrib) {
+      const int32_t gi = S.gauss[c], v = S.view[c], p = S.pixel[c];
+      if (gi >= 0 && gi < N && v >= 0 && v < S.n_views) {             // else outside the live set: ignored
+        const SelView sv = S.views[v];
+        if (p >= 0 && (int64_t)p < sv.pixels) {
+          g = gi;
+          const float e = S.maps[sv.out_offset + p] * S.weight[c];   // one FP32 product
+          if (e > 0.0f) q = (uint64_t)floor((double)e * 4294967296.0);  // exact: fl32 times 2^32
+        }
+      }
+    }
+    const int32_t gp = __shfl_up(g, 1, 64);
+    const bool head = lane == 0 || gp != g;
+    const uint64_t heads = __ballot(head);
+    const int rid = __popcll(heads & ((2ull << lane) - 1ull));        // run of this lane
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t qo = __shfl_down(q, o, 64);
+      const int ro = __shfl_down(rid, o, 64);
+      if (lane + o < 64 && ro == rid) q += qo;
+    }
+    if (head && g >= 0 && q != 0) atomicAdd(reinterpret_cast<unsigned long long*>(S.scores + g), (unsigned long long)q);
   }
 }
 

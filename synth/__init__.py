@@ -52,7 +52,7 @@ def lib():
         L.syn_mask.argtypes = [u64, i64, i64, vp]
         L.syn_contrib_count.argtypes = [u64, i64, i32, vp, vp, i32, vp]
         L.syn_contrib_count.restype = i64
-        L.syn_contrib_fill.argtypes = [u64, i64, i32, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.syn_contrib_fill.argtypes = [u64, i64, i32, vp, vp, i32, vp, i32, vp, vp, vp, vp]
         for f in ("syn_image", "syn_image_down2", "syn_image_batch", "syn_view_sizes",
                   "syn_gaussians", "syn_mask", "syn_contrib_fill"):
             getattr(L, f).restype = None
@@ -205,16 +205,18 @@ class Contributions:
         return int(self.gauss.shape[0])
 
 
-def contributions(seed: int, n_gauss: int, widths, heights, mean_radius: int = 3) -> Contributions:
+def contributions(seed: int, n_gauss: int, widths, heights, mean_radius: int = 3, order: str = "rows") -> Contributions:
     """Synthetic contributions of n_gauss Gaussians over views of the given
-    sizes (each Gaussian a clipped disc in one view; see synth.c)."""
+    sizes (each Gaussian a clipped disc in one view; see synth.c). order
+    "rows": grouped by view and image row, as a rasteriser meets them;
+    "spread": neighbouring entries belong to different Gaussians."""
     W = np.ascontiguousarray(widths, np.int32)
     H = np.ascontiguousarray(heights, np.int32)
     off = np.zeros(n_gauss + 1, np.int64)
     n = lib().syn_contrib_count(seed, n_gauss, int(W.size), _p(W), _p(H), int(mean_radius), _p(off))
     c = Contributions(np.zeros(n, np.int32), np.zeros(n, np.int32), np.zeros(n, np.int32), np.zeros(n, np.float32))
-    lib().syn_contrib_fill(seed, n_gauss, int(W.size), _p(W), _p(H), int(mean_radius), _p(off), _p(c.gauss),
-                           _p(c.view), _p(c.pixel), _p(c.weight))
+    lib().syn_contrib_fill(seed, n_gauss, int(W.size), _p(W), _p(H), int(mean_radius), _p(off),
+                           {"spread": 0, "rows": 1}[order], _p(c.gauss), _p(c.view), _p(c.pixel), _p(c.weight))
     return c
 
 

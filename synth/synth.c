@@ -293,9 +293,10 @@ void syn_mask(uint64_t seed, int64_t N, int64_t K, uint8_t* mask) {
  * view, clipped to the view, with weight a * exp(-d^2 / (2 (r/2)^2)) for a
  * per-Gaussian opacity a in [0.05, 1). Everything about Gaussian g is drawn
  * from a generator keyed by (seed, g), so the lists of different Gaussians
- * are independent of each other and of the thread count. Entries are then
- * spread by the bijection i -> (i * P) mod n (P prime, not dividing n), so
- * neighbouring entries belong to different Gaussians.
+ * are independent of each other and of the thread count. Order 0 spreads
+ * the entries by the bijection i -> (i * P) mod n (P prime, not dividing n),
+ * so neighbouring entries belong to different Gaussians; order 1 is the row
+ * order below.
  */
 typedef struct {
   int32_t v, cx, cy, r;
@@ -342,11 +343,61 @@ static int64_t gcd64(int64_t a, int64_t b) {
   return a;
 }
 
+/* Row order: entries grouped by (view, row), rows of a view in order, and
+ * inside a row by Gaussian (each Gaussian's pixels of that row contiguous,
+ * left to right) -- the order a rasteriser walking the image would meet
+ * them in, up to the order of Gaussians within a row. */
+static void contrib_fill_rows(uint64_t seed, int64_t n_gauss, int32_t n_views, const int32_t* W, const int32_t* H,
+                              int32_t mean_radius, int64_t n, int32_t* gauss, int32_t* view, int32_t* pixel,
+                              float* weight) {
+  int64_t rows = 0;
+  int64_t* row0 = (int64_t*)malloc(sizeof(int64_t) * (n_views + 1));
+  for (int v = 0; v < n_views; ++v) { row0[v] = rows; rows += H[v]; }
+  row0[n_views] = rows;
+  int64_t* cur = (int64_t*)calloc(rows + 1, sizeof(int64_t));
+  for (int64_t g = 0; g < n_gauss; ++g) {   /* entries per (view, row) */
+    const foot_t f = footprint(seed, g, n_views, W, H, mean_radius);
+    for (int dy = -f.r; dy <= f.r; ++dy) {
+      const int y = f.cy + dy;
+      if (y < 0 || y >= H[f.v]) continue;
+      for (int dx = -f.r; dx <= f.r; ++dx) {
+        const int x = f.cx + dx;
+        if (dx * dx + dy * dy <= f.r * f.r && x >= 0 && x < W[f.v]) ++cur[row0[f.v] + y + 1];
+      }
+    }
+  }
+  for (int64_t r = 0; r < rows; ++r) cur[r + 1] += cur[r];
+  for (int64_t g = 0; g < n_gauss; ++g) {
+    const foot_t f = footprint(seed, g, n_views, W, H, mean_radius);
+    const double s2 = 2.0 * (0.5 * f.r) * (0.5 * f.r);
+    for (int dy = -f.r; dy <= f.r; ++dy) {
+      const int y = f.cy + dy;
+      if (y < 0 || y >= H[f.v]) continue;
+      for (int dx = -f.r; dx <= f.r; ++dx) {
+        const int x = f.cx + dx;
+        if (dx * dx + dy * dy > f.r * f.r || x < 0 || x >= W[f.v]) continue;
+        const int64_t o = cur[row0[f.v] + y]++;
+        gauss[o] = (int32_t)g;
+        view[o] = f.v;
+        pixel[o] = y * W[f.v] + x;
+        weight[o] = (float)(f.a * exp(-(double)(dx * dx + dy * dy) / s2));
+      }
+    }
+  }
+  (void)n;
+  free(cur);
+  free(row0);
+}
+
 void syn_contrib_fill(uint64_t seed, int64_t n_gauss, int32_t n_views, const int32_t* W, const int32_t* H,
-                      int32_t mean_radius, const int64_t* offsets, int32_t* gauss, int32_t* view, int32_t* pixel,
-                      float* weight) {
+                      int32_t mean_radius, const int64_t* offsets, int32_t order, int32_t* gauss, int32_t* view,
+                      int32_t* pixel, float* weight) {
   const int64_t n = offsets[n_gauss];
   if (n == 0) return;
+  if (order == 1) {
+    contrib_fill_rows(seed, n_gauss, n_views, W, H, mean_radius, n, gauss, view, pixel, weight);
+    return;
+  }
   int64_t P = 1000003;  /* prime; step to the next prime-ish value until coprime with n */
   while (gcd64(P, n) != 1) P += 2;
 #pragma omp parallel for schedule(dynamic, 4096)

@@ -51,6 +51,7 @@ def run(N, cap, W, H, c, grad, thr, warm, budget, maps, off, extra_bad=False):
     return ref_k
 
 
+@pytest.mark.parametrize("order", ["rows", "spread"])
 @pytest.mark.parametrize("N,radius,thr,warm,budget_extra", [
     (1000, 3, 3e-4, False, 300),
     (2048, 2, 1e-4, False, 10 ** 6),      # budget above the candidates: every candidate
@@ -58,10 +59,10 @@ def run(N, cap, W, H, c, grad, thr, warm, budget, maps, off, extra_bad=False):
     (5000, 1, 5e-4, False, 0),            # budget == N: nothing
     (70001, 4, 1.5e-4, False, 7000),
 ])
-def test_split_mask_parity(N, radius, thr, warm, budget_extra):
+def test_split_mask_parity(N, radius, thr, warm, budget_extra, order):
     W, H = [320, 257, 96], [200, 133, 61]
     maps, off = _maps(N, W, H)
-    c = synth.contributions(N + 1, N, W, H, radius)
+    c = synth.contributions(N + 1, N, W, H, radius, order)
     grad = synth.grad_accum(N + 2, N)
     K = run(N, N + 123, W, H, c, grad, thr, warm, N + budget_extra, maps, off, extra_bad=True)
     print(N, "K", K, "contributions", c.n)
