@@ -8,7 +8,14 @@
  *                       gradient, median normalisation;
  *   long_axis_split  -- Long-Axis-Split of selected Gaussians (Sec. 2.2,
  *                       Algorithm 1 with the column-extraction transform of
- *                       Algorithm 2).
+ *                       Algorithm 2); long_axis_split_full also carries
+ *                       features of any width and the children's optimiser
+ *                       state;
+ *   split_mask       -- which Gaussians to split: edge scores moved onto the
+ *                       Gaussians, gradient threshold with warm-up, budget;
+ * plus the tile/form autotuner (igsp_edge_autotune, igsp_edge_resolve), one
+ * densification step as a HIP graph (igsp_step_*) and the exponential
+ * learning-rate schedule (igsp_lr_exponential, host only).
  *
  * Conventions for every entry point:
  *   - Pointers marked (device) are HIP device memory on the current device;
