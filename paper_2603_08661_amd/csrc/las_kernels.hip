@@ -179,37 +179,95 @@ __device__ __forceinline__ void split_row(const LasLaunch& L, int64_t i, int64_t
   L.split_idx[rank] = (int32_t)i;
 }
 
-// Row-wide work for the `total` selected rows of a tile, spread over the
-// work-group with consecutive lanes on consecutive words of a row: the
-// second child's features copied from the parent, and the given moment rows
-// of both children cleared.
-__device__ __forceinline__ void zero_rows(float* a, int w, const int32_t* rows, int64_t base, int64_t N,
-                                          int64_t first, int total) {
-  if (!a) return;
-  for (int k = threadIdx.x; k < total * w; k += kLasThreads) {
-    const int r = k / w, e = k - r * w;
-    a[(base + rows[r]) * w + e] = 0.0f;
-    a[(N + first + r) * w + e] = 0.0f;
+// Row-wide work for the `total` selected rows of a tile: the second
+// children's feature rows copied from the parents, and the given moment rows
+// of both children cleared. The second children of a tile are consecutive
+// rows, so their moment rows form one contiguous span, cleared with 16-byte
+// stores; a parent's row of width w is handled by w consecutive lanes, 64 / w
+// rows per wavefront step (the lane's row and element come from divisions
+// done once).
+
+// Zero n floats from p (p 4-byte aligned): 16-byte stores in the aligned middle.
+__device__ __forceinline__ void zero_span(float* p, int64_t n) {
+  const int head = (int)min<int64_t>(n, ((16 - (int)(reinterpret_cast<uintptr_t>(p) & 15)) & 15) / 4);
+  if (threadIdx.x < head) p[threadIdx.x] = 0.0f;
+  float* q = p + head;
+  const int64_t m = n - head, m4 = m / 4;
+  for (int64_t k = threadIdx.x; k < m4; k += kLasThreads)
+    reinterpret_cast<float4*>(q)[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int64_t k = 4 * m4 + threadIdx.x; k < m; k += kLasThreads) q[k] = 0.0f;
+}
+
+// Lane layout for rows of width w (1 <= w): rows per wavefront step and this
+// lane's (row, element), or a whole row per step split over 64-lane chunks.
+struct RowLanes {
+  int rpw;    // rows per wavefront step (0: one row, elements strided by 64)
+  int lr, le; // this lane's row within the step and element
+};
+
+__device__ __forceinline__ RowLanes row_lanes(int w) {
+  const int lane = threadIdx.x & 63;
+  RowLanes r;
+  if (w <= 64) {
+    r.rpw = 64 / w;
+    r.lr = lane / w;
+    r.le = lane - r.lr * w;
+    if (r.lr >= r.rpw) r.lr = -1;  // lanes past the last whole row idle
+  } else {
+    r.rpw = 0;
+    r.lr = 0;
+    r.le = lane;
+  }
+  return r;
+}
+
+// a[parent row] = 0 for the tile's selected rows.
+__device__ __forceinline__ void zero_parents(float* a, int w, const RowLanes& rl, const int32_t* rows, int64_t base,
+                                             int total) {
+  const int wv = threadIdx.x >> 6;
+  constexpr int NWV = kLasThreads / 64;
+  if (rl.rpw > 0) {
+    if (rl.lr < 0) return;
+    for (int r = wv * rl.rpw + rl.lr; r < total; r += NWV * rl.rpw) a[(base + rows[r]) * w + rl.le] = 0.0f;
+  } else {
+    for (int r = wv; r < total; r += NWV)
+      for (int e = rl.le; e < w; e += 64) a[(base + rows[r]) * w + e] = 0.0f;
   }
 }
 
 __device__ __forceinline__ void row_work(const LasLaunch& L, const int32_t* rows, int64_t base, int64_t N,
                                          int64_t first, int total) {
   const int F = L.g.feat_dim;
-  if (F > 0) {
+  const int wv = threadIdx.x >> 6;
+  constexpr int NWV = kLasThreads / 64;
+  if (F > 0) {  // second children's features from the parents
+    const RowLanes rl = row_lanes(F);
     float* f = L.g.features;
-    for (int k = threadIdx.x; k < total * F; k += kLasThreads) {
-      const int r = k / F, e = k - r * F;
-      f[(N + first + r) * F + e] = f[(base + rows[r]) * F + e];
+    if (rl.rpw > 0) {
+      if (rl.lr >= 0)
+        for (int r = wv * rl.rpw + rl.lr; r < total; r += NWV * rl.rpw)
+          f[(N + first + r) * F + rl.le] = f[(base + rows[r]) * F + rl.le];
+    } else {
+      for (int r = wv; r < total; r += NWV)
+        for (int e = rl.le; e < F; e += 64) f[(N + first + r) * F + e] = f[(base + rows[r]) * F + e];
     }
   }
   const igsp_adam_moments& A = L.adam;
-  for (int m = 0; m < 2; ++m) {
-    zero_rows(A.means[m], 3, rows, base, N, first, total);
-    zero_rows(A.log_scales[m], 3, rows, base, N, first, total);
-    zero_rows(A.quats[m], 4, rows, base, N, first, total);
-    zero_rows(A.opacity_logits[m], 1, rows, base, N, first, total);
-    zero_rows(A.features[m], F, rows, base, N, first, total);
+  float* const arr[5][2] = {{A.means[0], A.means[1]}, {A.log_scales[0], A.log_scales[1]},
+                            {A.quats[0], A.quats[1]}, {A.opacity_logits[0], A.opacity_logits[1]},
+                            {A.features[0], A.features[1]}};
+  const int width[5] = {3, 3, 4, 1, F};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    if (width[k] == 0 || (!arr[k][0] && !arr[k][1])) continue;
+    const RowLanes rl = row_lanes(width[k]);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      float* a = arr[k][m];
+      if (!a) continue;
+      zero_parents(a, width[k], rl, rows, base, total);
+      zero_span(a + (N + first) * width[k], (int64_t)total * width[k]);
+    }
   }
 }
 
