@@ -8,6 +8,7 @@ a brute-force re-formulation of the suppression step written a different way
 (angle-based direction table instead of exact integer bins).
 """
 import json
+import math
 import os
 from fractions import Fraction
 
@@ -263,3 +264,92 @@ def test_batch_equals_single_views_any_threads():
 def test_rejects_views_below_3x3():
     with pytest.raises(ValueError):
         oracle.edge_view(np.zeros((2, 5, 3), np.uint8))
+
+
+# ---------------------------------------------------------------- exact brute force, whole pipeline
+
+def _brute_pipeline(im):
+    """Every step of Sec. 2.1 in plain Python integers on a small image, with
+    formulations that differ from the oracle's: explicit reflect-101 by
+    repeated mirroring, the 5x5 blur as one 25-term sum, the orientation from
+    the exact comparison (|gx| + |gy|)^2 vs 2 g^2, the median by sorting.
+    Returns (keep, M, M of the median survivor or None)."""
+    H, W = im.shape[:2]
+
+    def refl(i, n):
+        while i < 0 or i >= n:
+            i = -i if i < 0 else 2 * (n - 1) - i
+        return i
+
+    g = [[299 * int(im[y, x, 0]) + 587 * int(im[y, x, 1]) + 114 * int(im[y, x, 2]) for x in range(W)]
+         for y in range(H)]
+    w = [1, 4, 6, 4, 1]
+    b = [[sum(w[j] * w[k] * g[refl(y + j - 2, H)][refl(x + k - 2, W)] for j in range(5) for k in range(5))
+          for x in range(W)] for y in range(H)]
+
+    def B(y, x):
+        return b[refl(y, H)][refl(x, W)]
+
+    gx = [[sum(c * (B(y + dy, x + 1) - B(y + dy, x - 1)) for dy, c in ((-1, 1), (0, 2), (1, 1))) for x in range(W)]
+          for y in range(H)]
+    gy = [[sum(c * (B(y + 1, x + dx) - B(y - 1, x + dx)) for dx, c in ((-1, 1), (0, 2), (1, 1))) for x in range(W)]
+          for y in range(H)]
+    M = [[gx[y][x] ** 2 + gy[y][x] ** 2 for x in range(W)] for y in range(H)]
+
+    def sgn(v):
+        return (v > 0) - (v < 0)
+
+    keep = [[0] * W for _ in range(H)]
+    for y in range(H):
+        for x in range(W):
+            a, c = gx[y][x], gy[y][x]
+            s = (abs(a) + abs(c)) ** 2
+            if s < 2 * a * a:
+                d = (sgn(a), 0)
+            elif s < 2 * c * c:
+                d = (0, sgn(c))
+            else:
+                d = (sgn(a), sgn(c))
+            m = M[y][x]
+            lo = M[refl(y - d[1], H)][refl(x - d[0], W)]
+            hi = M[refl(y + d[1], H)][refl(x + d[0], W)]
+            keep[y][x] = int(m > 0 and m > lo and m >= hi)
+    surv = sorted(M[y][x] for y in range(H) for x in range(W) if keep[y][x])
+    mmed = surv[(len(surv) - 1) // 2] if surv else None
+    return np.array(keep, np.uint8), np.array(M, dtype=object), mmed
+
+
+def _tiny_images():
+    rng = np.random.default_rng(17)
+    out = [rng.integers(0, 256, (8, 8, 3), dtype=np.uint8) for _ in range(12)]
+    out += [rng.integers(120, 124, (8, 8, 3), dtype=np.uint8) for _ in range(4)]     # many ties
+    yy, xx = np.mgrid[0:8, 0:8]
+    out.append(np.repeat(((xx + yy) % 2 * 255).astype(np.uint8)[..., None], 3, 2))  # checkerboard
+    st = np.zeros((8, 8, 3), np.uint8)
+    st[:, 4:] = 200
+    out.append(st)                                                                    # step
+    out.append(np.repeat((xx * 30).astype(np.uint8)[..., None], 3, 2))               # ramp
+    out.append(rng.integers(0, 256, (3, 5, 3), dtype=np.uint8))                      # smallest views
+    out.append(rng.integers(0, 256, (5, 3, 3), dtype=np.uint8))
+    return out
+
+
+@pytest.mark.parametrize("k", range(21))
+def test_whole_pipeline_against_exact_brute_force(k):
+    im = _tiny_images()[k]
+    keep, M, mmed = _brute_pipeline(im)
+    o = oracle.edge_view(im)
+    assert (o["M"] == M.astype(np.int64)).all()
+    assert (o["keep"] == keep).all()
+    assert o["n"] == int(keep.sum())
+    if mmed is None:
+        assert (o["E"] == 0).all()
+        return
+    # the median survivor's magnitude, exactly; in DN of an unnormalised Sobel: sqrt(M_med) / 256000
+    assert int(o["Mmed"]) == mmed
+    assert o["med"] == pytest.approx(math.sqrt(mmed) / 256000.0, rel=1e-15)
+    # the map squared is M / M_med exactly (up to the FP64 root and division)
+    for y, x in zip(*np.nonzero(keep)):
+        want = Fraction(int(M[y, x]), mmed)
+        assert o["E"][y, x] ** 2 == pytest.approx(float(want), rel=4e-16 * 8)
+    assert (o["E"][keep == 0] == 0).all()
