@@ -211,7 +211,7 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner on this batch first (default: the library's tuned table)")
     ap.add_argument("--form", default="batched", choices=["batched", "staged", "persistent"],
-                    help="batched launch form (batched: autotuned between staged and persistent)")
+                    help="batched launch form (batched: the tuned table's choice, else staged)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (counter calibration)")
     ap.add_argument("--summarise-profile", default=None, metavar="DIR",
