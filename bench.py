@@ -80,8 +80,6 @@ def summarise_profile(d: str, copy_bytes: int):
     """Turn the rocprofv3 outputs under directory d (trace/, fetch/, write/,
     copy_fetch/, copy_write/ and bench.json, see the commands recorded in the
     summaries) into the two short summaries kept under profiles/."""
-    import hashlib
-
     res = json.loads(open(os.path.join(d, "bench.json")).read().strip().splitlines()[-1])
     kernel = res["roofline"]["kernel"]
     # the instantiation the timed form runs: <storage precision, wavefronts per work-group>
@@ -125,10 +123,9 @@ def summarise_profile(d: str, copy_bytes: int):
     f_write = copy_bytes / (cw * 1024) if cw else None
     traffic = (fetch * 1024 * f_fetch + write * 1024 * f_write) if None not in (fetch, write, f_fetch, f_write) \
         else None
-    src = os.path.join(ROOT, "paper_2603_08661_amd", "csrc", "edge_kernels.hip")
     pmc_cmd = "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --stage-reps 2"
     t = [f"kernel: {kernel}",
-         f"kernel_source_sha256: {hashlib.sha256(open(src, 'rb').read()).hexdigest()}",
+         f"kernel_source_sha256: {kernel_source_digest()}",
          f"workload: {wl}",
          f"precision: {res['config']['intermediate']}",
          f"tile: {res['config']['tile']}",
@@ -158,21 +155,29 @@ def summarise_profile(d: str, copy_bytes: int):
                       avg[0] / 1e6 if avg else None, "live_ms": res["stage_ms"]["fused"]}))
 
 
+def kernel_source_digest() -> str:
+    """SHA-256 over the stencil kernels and the host code that orders their
+    work-groups: counters taken on other sources do not describe this build."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("edge_kernels.hip", "igsp_api.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2603_08661_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def profile_facts(kernel: str, prec: str, workload: str, seg_rows: int, wg_waves: int) -> dict:
     """Counter facts (HBM bytes, VALU instructions per launch) of the dominant
     kernel from the committed summary, or {} when that summary was taken on
     another kernel source, workload, storage precision or tile shape."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_2603_08661_amd", "csrc", "edge_kernels.hip")
     try:
         kv = {}
         for line in open(path):
             if ":" in line and not line.startswith(" "):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        digest = kernel_source_digest()
         if (kv.get("kernel_source_sha256") != digest or kv.get("precision") != prec
                 or kv.get("workload") != workload or kv.get("tile") != f"{seg_rows}x{wg_waves}"):
             return {}

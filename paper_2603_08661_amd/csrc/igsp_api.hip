@@ -78,6 +78,7 @@ struct EdgePlan {
   int n_views = 0;
   ViewDesc* d_views = nullptr;
   EdgeItem* d_items = nullptr;
+  EdgeItem* d_items_all = nullptr;  // the same items in the order of a launch over every view
   FlatItem* d_flat = nullptr;
   std::vector<int> item_begin, flat_begin;  // per view, size n_views + 1
   void* d_map = nullptr;
@@ -95,7 +96,8 @@ struct EdgePlan {
   UfLaunch uf{};
   int64_t map_elems = 0;
   ~EdgePlan() {
-    (void)hipFree(d_views); (void)hipFree(d_items); (void)hipFree(d_flat); (void)hipFree(d_map);
+    (void)hipFree(d_views); (void)hipFree(d_items); (void)hipFree(d_items_all); (void)hipFree(d_flat);
+    (void)hipFree(d_map);
     (void)hipFree(d_hist); (void)hipFree(d_rhist); (void)hipFree(d_state);
     (void)hipFree(d_pflat); (void)hipFree(d_tasks); (void)hipFree(d_sync); (void)hipFree(d_ctl);
     (void)hipFree(const_cast<UfItem*>(uf.items)); (void)hipFree(uf.gray); (void)hipFree(uf.blur);
@@ -236,7 +238,22 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
   plan->item_begin[n] = (int)items.size();
   plan->flat_begin[n] = (int)flat.size();
   plan->map_elems = map_elems;
+  // A launch over every view gives each XCD a contiguous eighth of the list
+  // (the kernel's block remap); inside each eighth, full bands come first and
+  // the shorter last bands of the strips after them, longest first, so the
+  // short waves fill the XCD while its last long ones finish.
+  std::vector<EdgeItem> all(items);
+  {
+    const int64_t ni = (int64_t)all.size(), q = ni >> 3, r = ni & 7;
+    for (int64_t x = 0, b = 0; x < 8; ++x) {
+      const int64_t e = b + q + (x < r ? 1 : 0);
+      std::stable_sort(all.begin() + b, all.begin() + e,
+                       [](const EdgeItem& u, const EdgeItem& v) { return u.rows > v.rows; });
+      b = e;
+    }
+  }
   if (upload(&plan->d_views, vd) != hipSuccess || upload(&plan->d_items, items) != hipSuccess ||
+      upload(&plan->d_items_all, all) != hipSuccess ||
       upload(&plan->d_flat, flat) != hipSuccess)
     return IGSP_ERR_HIP;
   if (hipMalloc(&plan->d_map, (size_t)std::max<int64_t>(map_elems, 64) * esz) != hipSuccess) return IGSP_ERR_HIP;
@@ -430,6 +447,11 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
     return e;
   };
   auto stencil = [&](int v0, int v1, hipStream_t st) -> hipError_t {
+    if (v0 == 0 && v1 == n) {
+      EdgeLaunch LA = L;
+      LA.items = P->d_items_all;
+      return launch_edge_fused(LA, 0, P->item_begin[n], st);
+    }
     return launch_edge_fused(L, P->item_begin[v0], P->item_begin[v1] - P->item_begin[v0], st);
   };
   auto norm = [&](int v0, int v1, hipStream_t st) -> hipError_t {
