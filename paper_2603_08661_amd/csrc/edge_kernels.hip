@@ -103,6 +103,26 @@ __device__ __forceinline__ int fold_near(int i, int n) {
 
 __device__ __forceinline__ int mad24(int a, int b, int c) { return (int)__umul24((unsigned)a, (unsigned)b) + c; }
 
+// 6 a + c in one instruction (a < 2^24): kept opaque so that the sum c is
+// formed first (two instructions) and not re-associated around a separate
+// multiply (three).
+__device__ __forceinline__ int mad6(int a, int c) {
+  int r;
+  asm("v_mad_u32_u24 %0, %1, 6, %2" : "=v"(r) : "v"(a), "v"(c));
+  return r;
+}
+
+// 4 k + c for the 16-bit half k of w (HI: bits 16..31), one instruction:
+// the byte offset of histogram bin k - lo from the histogram's start when
+// c = -4 lo (mod 2^32).
+template <bool HI>
+__device__ __forceinline__ uint32_t half_x4_plus(uint32_t w, uint32_t c) {
+  uint32_t r;
+  if constexpr (HI) asm("v_mad_u32_u16 %0, %1, 4, %2 op_sel:[1,0,0,0]" : "=v"(r) : "v"(w), "s"(c));
+  else asm("v_mad_u32_u16 %0, %1, 4, %2" : "=v"(r) : "v"(w), "s"(c));
+  return r;
+}
+
 // ------------------------------------------------------------- storage
 
 template <int PREC> struct Store;
@@ -250,7 +270,7 @@ struct StripState {
   int h[2][4];                     // the horizontal blur
   int tv[2][4];                    // its first vertical (1 2 1) pass
   int sx[2][4];                    // the horizontal difference of the blur
-  int b[2][4];                     // the blur
+  int hs[2][4];                    // the horizontal (1 2 1) smoothing of the blur
   float M[3][4];                   // squared magnitude of the last three rows
   float ML[3], MR[3];              // and the lanes' outer neighbours of each
   float fx[2][4], fy[2][4];        // gradient of the last two rows (exact in float for |g| < 2^24,
@@ -314,10 +334,10 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   const int gL2 = from_left(g[2]), gL3 = from_left(g[3]);
   const int gR0 = from_right(g[0]), gR1 = from_right(g[1]);
   int h[4];
-  h[0] = mad24(g[0], 6, (gL2 + g[2]) + 4 * (gL3 + g[1]));
-  h[1] = mad24(g[1], 6, (gL3 + g[3]) + 4 * (g[0] + g[2]));
-  h[2] = mad24(g[2], 6, (g[0] + gR0) + 4 * (g[1] + g[3]));
-  h[3] = mad24(g[3], 6, (g[1] + gR1) + 4 * (g[2] + gR0));
+  h[0] = mad6(g[0], (gL2 + g[2]) + 4 * (gL3 + g[1]));
+  h[1] = mad6(g[1], (gL3 + g[3]) + 4 * (g[0] + g[2]));
+  h[2] = mad6(g[2], (g[0] + gR0) + 4 * (g[1] + g[3]));
+  h[3] = mad6(g[3], (g[1] + gR1) + 4 * (g[2] + gR0));
 
   // ---- 3. vertical taps (1 4 6 4 1) = (1 2 1) twice: b = blur of row yy-2
   int b[4];
@@ -330,20 +350,20 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   }
 
   // ---- 4. Sobel of row yy-3: gx = (1 2 1)^T on the horizontal difference,
-  //      gy = (1 2 1) along x on the vertical difference b(r+1) - b(r-1)
+  //      gy = the vertical difference hs(r+1) - hs(r-1) of the horizontal
+  //      (1 2 1) smoothing (equal to smoothing the difference: the taps are
+  //      linear), so both use the same two lane-edge neighbours of b
   const int bL = from_left(b[3]), bR = from_right(b[0]);
   const int sxn[4] = {b[1] - bL, b[2] - b[0], b[3] - b[1], bR - b[2]};
-  int gx[4], sy[4];
+  const int hsn[4] = {bL + 2 * b[0] + b[1], b[0] + 2 * b[1] + b[2], b[1] + 2 * b[2] + b[3], b[2] + 2 * b[3] + bR};
+  int gx[4], gy[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     gx[i] = S.sx[P][i] + 2 * S.sx[Q][i] + sxn[i];          // (1 2 1) down the column
     S.sx[P][i] = sxn[i];
-    sy[i] = b[i] - S.b[P][i];          // the same parity slot still holds b(r-2)
-    S.b[P][i] = b[i];
+    gy[i] = hsn[i] - S.hs[P][i];       // the same parity slot still holds hs(r-2)
+    S.hs[P][i] = hsn[i];
   }
-  const int syL = from_left(sy[3]), syR = from_right(sy[0]);
-  const int gy[4] = {syL + 2 * sy[0] + sy[1], sy[0] + 2 * sy[1] + sy[2], sy[1] + 2 * sy[2] + sy[3],
-                     sy[2] + 2 * sy[3] + syR};
 
   // ---- 5. squared magnitude of row yy-3, and its lane-edge neighbours
 #pragma unroll
@@ -364,19 +384,20 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   const float* Mc = S.M[MC];
   const float* Md = S.M[MD];
   float q[4];
+  bool kept[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const float Ul = i > 0 ? Mu[i - 1] : S.ML[MU], Uc = Mu[i], Ur = i < 3 ? Mu[i + 1] : S.MR[MU];
     const float Cl = i > 0 ? Mc[i - 1] : S.ML[MC], Cr = i < 3 ? Mc[i + 1] : S.MR[MC];
     const float Dl = i > 0 ? Md[i - 1] : S.ML[MD], Dc = Md[i], Dr = i < 3 ? Md[i + 1] : S.MR[MD];
     const float m = Mc[i];
-    const bool keep = keep_of(direction(S.fx[Q][i], S.fy[Q][i]), m, Ul, Uc, Ur, Cl, Cr, Dl, Dc, Dr);
+    kept[i] = keep_of(direction(S.fx[Q][i], S.fy[Q][i]), m, Ul, Uc, Ur, Cl, Cr, Dl, Dc, Dr);
     const float v = St::kSquare ? m : __builtin_amdgcn_sqrtf(m) * kStoreScaleRoot;
-    q[i] = keep ? v : 0.0f;
+    q[i] = kept[i] ? v : 0.0f;
   }
   const __amdgpu_buffer_rsrc_t mrow =
       buffer_rsrc(C.map + (int64_t)max(c, 0) * C.W * ES, row_out ? C.W * ES : 0);
-  uint32_t bits[4];  // stored value widened to float32, for the histogram
+  uint32_t bits[4];  // words whose high halves are the histogram keys
   if constexpr (PREC == IGSP_FP32) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) bits[i] = __float_as_uint(q[i]);
@@ -389,9 +410,9 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   } else {
     const uint32_t w0 = St::pack2(q[0], q[1]), w1 = St::pack2(q[2], q[3]);
     bits[0] = w0 << 16;
-    bits[1] = w0 & 0xFFFF0000u;
+    bits[1] = w0;
     bits[2] = w1 << 16;
-    bits[3] = w1 & 0xFFFF0000u;
+    bits[3] = w1;
     if constexpr (ALIGNED) {
       __builtin_amdgcn_raw_buffer_store_b64(u32x2{w0, w1}, mrow, C.store_off[0], 0, CPOL);
     } else {
@@ -404,10 +425,27 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
       for (int i = 0; i < 4; ++i) bits[i] = __float_as_uint(St::widen((uint16_t)(bits[i] >> 16)));
     }
   }
+  // A survivor's stored value is never 0 and its key lies in [lo, lo + bins),
+  // so the keep decision selects the counted pixels and no clamp is needed:
+  // M is integer-valued in [1, 2^57) (|gx|, |gy| < 2^28), its float32 and
+  // BF16 patterns run from the exponent of 1 to below 2^58, and the FP16
+  // root sqrt(M) 2^-13 lies in [2^-13, 2^17) (normal, never rounded to 0).
+  // BF16 takes the keys of pixels 0 and 2 from the low halves of the stored
+  // words, everything else from high halves.
+  constexpr uint32_t kBase = 0u - 4u * Keys<PREC>::lo;
+  char* const hbytes = reinterpret_cast<char*>(hist);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
-    if (row_out && bits[i] != 0u && C.out_px[i])
-      atomicAdd(&hist[min(max((int)(bits[i] >> 16) - (int)Keys<PREC>::lo, 0), Keys<PREC>::bins - 1)], 1u);
+    if (row_out && kept[i] && C.out_px[i]) {
+      uint32_t off;
+      if constexpr (PREC == IGSP_BF16) {
+        const uint32_t w = i < 2 ? bits[1] : bits[3];
+        off = (i & 1) ? half_x4_plus<true>(w, kBase) : half_x4_plus<false>(w, kBase);
+      } else {
+        off = half_x4_plus<true>(bits[i], kBase);
+      }
+      atomicAdd(reinterpret_cast<uint32_t*>(hbytes + off), 1u);
+    }
 }
 
 template <int PREC, bool NARROW, bool ALIGNED, int CPOL>
