@@ -155,6 +155,34 @@ def summarise_profile(d: str, copy_bytes: int):
                       avg[0] / 1e6 if avg else None, "live_ms": res["stage_ms"]["fused"]}))
 
 
+def las_touched_bytes(mask: np.ndarray, K: int) -> int:
+    """Bytes of whole 128-byte lines the split moves: the mask, every line
+    holding a selected parent row of each array (read; written back for the
+    fields the split changes: means, log-scales, opacity), and the K
+    contiguous child rows plus their indices. With 20% of the rows selected
+    nearly every parent line is touched, so this approaches N x 44 read."""
+    idx = np.nonzero(mask)[0].astype(np.int64)
+
+    def lines(row_bytes):
+        first = idx * row_bytes // 128
+        last = (idx * row_bytes + row_bytes - 1) // 128
+        return np.unique(np.concatenate([first, last])).size * 128
+
+    parent = 2 * lines(12) + 2 * lines(12) + lines(16) + 2 * lines(4)   # means, log-scales, quats, opacity
+    return int(mask.size + parent + K * (44 + 4))
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (first entry of /proc/cpuinfo), or "unknown"."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def kernel_source_digest() -> str:
     """SHA-256 over the stencil kernels and the host code that orders their
     work-groups: counters taken on other sources do not describe this build."""
@@ -477,7 +505,7 @@ def main():
                           threads=1)
         t1c = time.perf_counter() - t1
         cpu = {"value": round(sub.pixels / 1e6 / te, 3), "unit": "MPx/s", "cores": threads, "kind": "oracle",
-               "value_1core": round(sub1.pixels / 1e6 / t1c, 3),
+               "value_1core": round(sub1.pixels / 1e6 / t1c, 3), "cpu_model": cpu_model(),
                "sample": f"edge maps of the first {nsamp} views ({sub.pixels / 1e6:.1f} MPx) of the same "
                          f"workload, views spread over {threads} threads, {te:.1f}s; on 1 core the first "
                          f"{n1} views ({sub1.pixels / 1e6:.1f} MPx), {t1c:.1f}s"}
@@ -539,8 +567,12 @@ def main():
     if has_las:
         res["gaussians_split_per_s"] = round(K / (ms * 1e-3), 1)
         las_bytes = N0 + 120 * K
+        touched = las_touched_bytes(mk[:N0], K)
         res["las"] = {"ms": round(las_ms, 4), "gaussians_split_per_s": round(K / (las_ms * 1e-3), 1),
-                      "algorithmic_GBps": round(las_bytes / (las_ms * 1e-3) / 1e9, 1)}
+                      "algorithmic_bytes": int(las_bytes),
+                      "algorithmic_GBps": round(las_bytes / (las_ms * 1e-3) / 1e9, 1),
+                      "touched_bytes": int(touched),
+                      "touched_GBps": round(touched / (las_ms * 1e-3) / 1e9, 1)}
     if select:
         res["split_mask"] = select
     if las_full:
