@@ -31,6 +31,13 @@ sys.path.insert(0, ROOT)
 METRIC = "edge-map megapixels/s + Gaussians split/s, batched-FP16 vs plain-FP32, % HBM peak"
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes per cycle x clock (non-packed)
+# Algorithmic work of the fused stencil: dynamic VALU lane-operations per
+# output pixel of its steady-state loop (an interior strip with 4-pixel
+# aligned stores), by storage precision -- what one pixel costs without the
+# halo rows and columns every strip recomputes, its set-up or the histogram
+# flush. Counted from the kernel's gfx950 code; a CPU test recompiles the
+# kernel and checks these figures against it.
+LOOP_LANE_OPS_PER_PX = {"fp32": 42.75, "fp16": 46.75, "bf16": 43.25}
 COPY_CAL_BYTES = 1 << 30
 STORE_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
 
@@ -119,6 +126,11 @@ def summarise_profile(d: str, copy_bytes: int):
                          "WRITE_SIZE")
     valu, nv = _counter_kib(_csv_rows(os.path.join(d, "valu", "**", "*counter_collection.csv")), sym,
                             "SQ_INSTS_VALU")
+    lds_rows = _csv_rows(os.path.join(d, "lds", "**", "*counter_collection.csv"))
+    lds, nl = _counter_kib(lds_rows, sym, "SQ_INSTS_LDS")
+    bank, _ = _counter_kib(lds_rows, sym, "SQ_LDS_BANK_CONFLICT")
+    idx_active, _ = _counter_kib(lds_rows, sym, "SQ_LDS_IDX_ACTIVE")
+    conflict_rate = bank / (idx_active - bank) if None not in (bank, idx_active) and idx_active > bank else None
     f_fetch = copy_bytes / (cf * 1024) if cf else None
     f_write = copy_bytes / (cw * 1024) if cw else None
     traffic = (fetch * 1024 * f_fetch + write * 1024 * f_write) if None not in (fetch, write, f_fetch, f_write) \
@@ -137,6 +149,10 @@ def summarise_profile(d: str, copy_bytes: int):
          f"traffic_bytes_per_launch: {traffic}",
          f"algorithmic_bytes_per_launch: {res['roofline']['bytes_per_launch']}",
          f"valu_insts_per_launch: {valu} ({nv} dispatches; SQ_INSTS_VALU, wave instructions)",
+         f"lds_insts_per_launch: {lds} ({nl} dispatches; SQ_INSTS_LDS, wave instructions)",
+         f"lds_bank_conflict_cycles_per_launch: {bank} (SQ_LDS_BANK_CONFLICT, cycles summed over CUs)",
+         f"lds_idx_active_cycles_per_launch: {idx_active} (SQ_LDS_IDX_ACTIVE)",
+         f"lds_bank_conflict_rate: {conflict_rate} (conflict cycles / conflict-free active cycles)",
          "",
          "  Commands (repo root, TMPDIR=/tmp), each pass in its own run:",
          f"    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/fetch -o p -- {pmc_cmd}",
@@ -147,6 +163,8 @@ def summarise_profile(d: str, copy_bytes: int):
          f"python3 bench.py --copy-calibration {copy_bytes}",
          f"    timeout -s KILL 120 rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES --output-format csv -d <dir>/valu -o p -- "
          f"{pmc_cmd}",
+         f"    timeout -s KILL 120 rocprofv3 --pmc SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE --output-format csv -d <dir>/lds "
+         f"-o p -- {pmc_cmd}",
          "    python3 bench.py --summarise-profile <dir>",
          "  FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by copy_bytes / (1024 x what the same",
          "  counter reads for the plain copy of copy_bytes bytes). traffic = scaled fetch + scaled write."]
@@ -195,9 +213,10 @@ def kernel_source_digest() -> str:
 
 
 def profile_facts(kernel: str, prec: str, workload: str, seg_rows: int, wg_waves: int) -> dict:
-    """Counter facts (HBM bytes, VALU instructions per launch) of the dominant
-    kernel from the committed summary, or {} when that summary was taken on
-    another kernel source, workload, storage precision or tile shape."""
+    """Counter facts (HBM bytes, VALU and LDS instructions, LDS bank-conflict
+    cycles per launch) of the dominant kernel from the committed summary, or
+    {} when that summary was taken on another kernel source, workload,
+    storage precision or tile shape."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic.txt")
     try:
         kv = {}
@@ -212,11 +231,16 @@ def profile_facts(kernel: str, prec: str, workload: str, seg_rows: int, wg_waves
     except OSError:
         return {}
     out = {}
-    for key in ("traffic_bytes_per_launch", "valu_insts_per_launch"):
+    for key in ("traffic_bytes_per_launch", "valu_insts_per_launch", "lds_insts_per_launch",
+                "lds_bank_conflict_cycles_per_launch"):
         try:
             out[key] = int(float(kv[key].split()[0]))
         except (KeyError, ValueError, IndexError):
             pass
+    try:
+        out["lds_bank_conflict_rate"] = round(float(kv["lds_bank_conflict_rate"].split()[0]), 4)
+    except (KeyError, ValueError, IndexError):
+        pass
     return out
 
 
@@ -526,17 +550,33 @@ def main():
 
     prof = profile_facts(kernel, prec, w.name, seg, wgw)
     traffic = prof.get("traffic_bytes_per_launch")
-    roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "algorithmic_bytes_per_px": per_px, "bytes_per_launch": int(fused_bytes)}
+    hbm = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_px": per_px,
+           "bytes_per_launch": int(fused_bytes)}
     if traffic:
         tg = traffic / (stage_ms["fused"] * 1e-3) / 1e9
-        roof["traffic_GBps"] = round(tg, 1)
-        roof["traffic_frac"] = round(tg / HBM_PEAK_GBS, 4)
+        hbm["traffic_GBps"] = round(tg, 1)
+        hbm["traffic_frac"] = round(tg / HBM_PEAK_GBS, 4)
+    if kernel == "edge_fused":
+        # bound by vector-ALU issue (counters: VALU busy ~85%, HBM ~43%):
+        # algorithmic lane-operations per launch against the VALU peak
+        ops = LOOP_LANE_OPS_PER_PX[prec] * vb.pixels
+        alu = ops / (stage_ms["fused"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": kernel, "achieved": round(alu, 2),
+                "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2), "unit": "TOP/s",
+                "frac": round(alu * 1e12 / VALU_PEAK_LANE_OPS, 4), "traffic": traffic,
+                "algorithmic_lane_ops_per_px": LOOP_LANE_OPS_PER_PX[prec], "ops_per_launch": int(ops),
+                "bytes_per_launch": int(fused_bytes), "hbm": hbm}
+    else:
+        roof = dict(hbm, bound="hbm", kernel=kernel, traffic=traffic)
     if prof.get("valu_insts_per_launch"):
         lane_ops = prof["valu_insts_per_launch"] * 64
         roof["valu_lane_ops_per_px"] = round(lane_ops / vb.pixels, 2)
         roof["valu_frac"] = round(lane_ops / (stage_ms["fused"] * 1e-3) / VALU_PEAK_LANE_OPS, 4)
+    if prof.get("lds_insts_per_launch") is not None:
+        roof["lds_insts_per_launch"] = prof["lds_insts_per_launch"]
+    if prof.get("lds_bank_conflict_rate") is not None:
+        roof["lds_bank_conflict_rate"] = prof["lds_bank_conflict_rate"]
     res = {
         "metric": METRIC,
         "value": round(mpx / (ms * 1e-3), 1),
