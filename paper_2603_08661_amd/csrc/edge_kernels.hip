@@ -101,8 +101,6 @@ __device__ __forceinline__ int fold_near(int i, int n) {
   return i;
 }
 
-__device__ __forceinline__ int mad24(int a, int b, int c) { return (int)__umul24((unsigned)a, (unsigned)b) + c; }
-
 // 6 a + c in one instruction (a < 2^24): kept opaque so that the sum c is
 // formed first (two instructions) and not re-associated around a separate
 // multiply (three).

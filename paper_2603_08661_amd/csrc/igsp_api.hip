@@ -564,9 +564,11 @@ struct SelPlan {
   uint32_t* d_counts = nullptr;
   int64_t* d_offsets = nullptr;
   SelState* d_state = nullptr;
+  SelRadix* d_ring = nullptr;
+  uint64_t* d_ckeys = nullptr;
   ~SelPlan() {
     (void)hipFree(d_views); (void)hipFree(d_hist); (void)hipFree(d_counts); (void)hipFree(d_offsets);
-    (void)hipFree(d_state);
+    (void)hipFree(d_state); (void)hipFree(d_ring); (void)hipFree(d_ckeys);
   }
 };
 std::list<std::shared_ptr<SelPlan>> g_sel_plans;
@@ -592,14 +594,16 @@ igsp_status get_sel_plan(const igsp_view* views, int32_t n_views, int64_t capaci
   std::vector<SelView> sv(n_views);
   for (int v = 0; v < n_views; ++v) sv[v] = SelView{views[v].out_offset, (int64_t)views[v].width * views[v].height};
   const int64_t tiles = std::max<int64_t>(1, (capacity + kSelTile - 1) / kSelTile);
+  // (the radix histograms and the key OR are cleared by each call's first
+  // kernel, so the plan needs no memset)
   if (upload(&plan->d_views, sv) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&plan->d_hist), 256 * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_hist), 3 * 256 * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&plan->d_counts), tiles * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&plan->d_offsets), tiles * sizeof(int64_t)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&plan->d_state), sizeof(SelState)) != hipSuccess)
-    return IGSP_ERR_HIP;
-  // the radix histogram starts at zero once; every pass clears what it read
-  if (hipMemset(plan->d_hist, 0, 256 * sizeof(uint32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+      hipMalloc(reinterpret_cast<void**>(&plan->d_state), sizeof(SelState)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_ring), 2 * sizeof(SelRadix)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&plan->d_ckeys), std::max<int64_t>(capacity, 1) * sizeof(uint64_t)) !=
+          hipSuccess)
     return IGSP_ERR_HIP;
   g_sel_plans.push_front(std::move(plan));
   while ((int)g_sel_plans.size() > kMaxPlans) g_sel_plans.pop_back();
@@ -644,6 +648,8 @@ extern "C" igsp_status split_mask(const float* maps, const igsp_view* views, int
   S.tile_counts = plan->d_counts;
   S.tile_offsets = plan->d_offsets;
   S.state = plan->d_state;
+  S.ring = plan->d_ring;
+  S.ckeys = plan->d_ckeys;
   const int64_t tiles = std::max<int64_t>(1, (capacity + kSelTile - 1) / kSelTile);
   S.grid = (int)std::min<int64_t>(tiles, kSelGrid);
   return launch_select(S, static_cast<hipStream_t>(stream)) == hipSuccess ? IGSP_OK : IGSP_ERR_HIP;

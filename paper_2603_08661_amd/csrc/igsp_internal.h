@@ -209,9 +209,19 @@ struct SelState {      // device scalars of one selection
   int64_t k;           // Gaussians to select
   int64_t candidates;
   int64_t ties;
+  uint64_t top;        // bitwise OR of the candidates' keys
   int32_t shift;       // low bits still unresolved
   int32_t pad;
 };
+
+struct SelRadix {      // the selection after one radix pass
+  uint64_t prefix;
+  int64_t rank;
+  int32_t shift;
+  int32_t pad;
+};
+
+constexpr int kSelPasses = 8;  // 8-bit digits of a 64-bit key
 
 struct SelLaunch {
   const float* maps;
@@ -231,7 +241,9 @@ struct SelLaunch {
   uint8_t* mask;
   int64_t* scores;
   int64_t* n_selected;
-  uint32_t* hist;           // [256], zero between passes
+  uint32_t* hist;           // [3][256]: pass p adds into slot p % 3, reads p - 1's
+  SelRadix* ring;           // [2]: the selection after pass p in slot p % 2
+  uint64_t* ckeys;          // [capacity]: the candidates' keys, in row order
   uint32_t* tile_counts;    // [tiles]
   int64_t* tile_offsets;    // [tiles]
   SelState* state;

@@ -2,20 +2,26 @@
 // takes (the selection that feeds it; Sec. 2.1's edge scores moved to the
 // Gaussians, Sec. 3's gradient threshold and warm-up, and a budget).
 //
-//   sel_clear   : scores[0, N) = 0 (a fill kernel, so the call can be captured)
+//   sel_clear   : scores[0, N) = 0, the radix histograms and the key OR = 0
+//                 (fill kernels, so the call can be captured)
 //   sel_scatter : per contribution (Gaussian g, view v, pixel p, weight w):
 //                 scores[g] += floor(fl32(E_v[p] * w) * 2^32), runs of equal
 //                 g on consecutive lanes summed first, then 64-bit atomics;
 //                 fixed point makes the sum exact and independent of the
 //                 order the additions land in
-//   sel_count   : candidates (warm-up, or grad[g] >= threshold) per tile
-//   sel_start   : K = min(candidates, max(0, budget - N)) and the first
-//                 radix digit
-//   sel_hist / sel_pick : exact radix selection, 8 bits at a time from the
-//                 top, of the K-th largest key, key = score + 1 for a
-//                 candidate and 0 otherwise
-//   sel_ties / sel_tie_scan / sel_mask : ties at the K-th key are taken in
-//                 ascending index order (per-tile counts, one scan, write)
+//   sel_count<0> / sel_scan<0> : candidates (warm-up, or grad[g] >=
+//                 threshold) per tile, their offsets, and
+//                 K = min(candidates, max(0, budget - N))
+//   sel_compact : the candidates' keys (score + 1) packed in row order, and
+//                 the OR of them (the highest digit any of them uses)
+//   sel_hist    : exact radix selection, 8 bits at a time from the highest
+//                 used digit, of the K-th largest key among the packed keys;
+//                 each pass first resolves the previous pass's digit from
+//                 that pass's histogram (every work-group alike), so no
+//                 separate launch picks the digit
+//   sel_count<1> / sel_scan<1> / sel_mask : the last digit, then ties at the
+//                 K-th key taken in ascending index order (per-tile counts,
+//                 one scan, write)
 #include "igsp_internal.h"
 
 namespace igsp {
@@ -38,6 +44,10 @@ __global__ __launch_bounds__(kSelThreads) void sel_clear_kernel(SelLaunch S) {
   const int64_t N = live_count(S);
   for (int64_t g = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; g < N; g += (int64_t)gridDim.x * kSelThreads)
     S.scores[g] = 0;
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < 3 * 256; i += kSelThreads) S.hist[i] = 0;
+    if (threadIdx.x == 0) S.state->top = 0;
+  }
 }
 
 // Contributions arrive in image order, so neighbouring entries often name the
@@ -99,14 +109,29 @@ __device__ __forceinline__ uint32_t sel_scan(uint32_t v, uint32_t* wsum, uint32_
   return before + x - v;
 }
 
+__device__ __forceinline__ void radix_pick(const uint32_t* cnt, SelRadix& r, uint32_t* wsum, int64_t* pick);
+
 // Per tile of kSelTile rows: candidates (mode 0) or keys equal to the
-// selected K-th key (mode 1).
+// selected K-th key (mode 1, which first resolves the last digit from the
+// last radix pass's histogram; work-group 0 records the result).
 template <int MODE>
 __global__ __launch_bounds__(kSelThreads) void sel_count_kernel(SelLaunch S) {
   __shared__ uint32_t wsum[kSelThreads / 64];
+  __shared__ int64_t pick[2];
   const int64_t N = live_count(S);
   const int nt = (int)((N + kSelTile - 1) / kSelTile);
-  const uint64_t T = MODE == 1 ? S.state->kth : 0;
+  uint64_t T = 0;
+  if (MODE == 1) {
+    SelRadix r = S.ring[(kSelPasses - 1) & 1];
+    if (r.shift > 0) radix_pick(S.hist + ((kSelPasses - 1) % 3) * 256, r, wsum, pick);
+    T = r.prefix;  // every digit resolved: the K-th largest key (0 when K = 0)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      S.state->prefix = r.prefix;
+      S.state->kth = r.prefix;
+      S.state->rank = r.rank;
+      S.state->shift = r.shift;
+    }
+  }
   for (int t = blockIdx.x; t < nt; t += gridDim.x) {
     uint32_t c = 0;
     for (int k = 0; k < kSelTile / kSelThreads; ++k) {
@@ -161,7 +186,7 @@ __global__ __launch_bounds__(1024) void sel_scan_kernel(SelLaunch S) {
       st->prefix = 0;
       st->rank = K;          // the K-th largest key: K - 1 keys above it
       st->shift = 64;
-      st->kth = 0;
+      st->kth = 0;           // (the radix passes keep their progress in the ring)
       if (S.n_selected) *S.n_selected = K;
     } else {
       st->ties = total;
@@ -169,47 +194,95 @@ __global__ __launch_bounds__(1024) void sel_scan_kernel(SelLaunch S) {
   }
 }
 
-// One radix pass: histogram of the next 8-bit digit of the keys whose
-// already-resolved high bits equal the prefix.
-__global__ __launch_bounds__(kSelThreads) void sel_hist_kernel(SelLaunch S) {
-  __shared__ uint32_t h[256];
-  const SelState st = *S.state;
-  if (st.k == 0 || st.shift == 0) return;  // nothing to select / resolved
-  h[threadIdx.x] = 0;
-  __syncthreads();
+// Packs the candidates' keys in row order (tile offsets from sel_scan<0>)
+// and ORs them into the state: the highest set bit of the OR bounds every
+// candidate key, so the radix passes start at the highest digit in use.
+__global__ __launch_bounds__(kSelThreads) void sel_compact_kernel(SelLaunch S) {
+  __shared__ uint32_t wsum[kSelThreads / 64];
+  __shared__ uint64_t wor[kSelThreads / 64];
   const int64_t N = live_count(S);
-  const int shift = st.shift - 8;
-  for (int64_t g = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; g < N; g += (int64_t)gridDim.x * kSelThreads) {
-    const uint64_t key = key_of(S, g);
-    if (st.shift == 64 || (key >> st.shift) == st.prefix) atomicAdd(&h[(key >> shift) & 255u], 1u);
+  const int nt = (int)((N + kSelTile - 1) / kSelTile);
+  uint64_t acc = 0;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    int64_t before = S.tile_offsets[t];
+    for (int k = 0; k < kSelTile / kSelThreads; ++k) {
+      const int64_t g = (int64_t)t * kSelTile + k * kSelThreads + threadIdx.x;
+      const bool cand = g < N && candidate(S, g);
+      const uint64_t key = cand ? (uint64_t)S.scores[g] + 1ull : 0ull;
+      uint32_t total = 0;
+      const uint32_t r = sel_scan(cand ? 1u : 0u, wsum, total);
+      if (cand) S.ckeys[before + r] = key;
+      acc |= key;
+      before += total;
+    }
   }
-  __syncthreads();
-  const uint32_t c = h[threadIdx.x];
-  if (c) atomicAdd(&S.hist[threadIdx.x], c);
-}
-
-// Pick the digit holding the rank-th largest key among the prefix's keys.
-__global__ __launch_bounds__(256) void sel_pick_kernel(SelLaunch S) {
-  __shared__ uint32_t cnt[256];
-  SelState st = *S.state;
-  const uint32_t c = S.hist[threadIdx.x];
-  S.hist[threadIdx.x] = 0;  // ready for the next pass or call
-  if (st.k == 0 || st.shift == 0) return;
-  cnt[threadIdx.x] = c;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc |= __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) wor[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
-    int64_t rank = st.rank;  // 1-based from the top
-    int d = 255;
-    for (; d > 0; --d) {
-      if ((int64_t)cnt[d] >= rank) break;
-      rank -= cnt[d];
-    }
-    st.prefix = (st.prefix << 8) | (uint64_t)d;
-    st.shift -= 8;
-    st.rank = rank;
-    if (st.shift == 0) st.kth = st.prefix;
-    *S.state = st;
+    uint64_t a = 0;
+    for (int w = 0; w < kSelThreads / 64; ++w) a |= wor[w];
+    if (a) atomicOr(reinterpret_cast<unsigned long long*>(&S.state->top), (unsigned long long)a);
   }
+}
+
+// Resolves the digit of a radix pass from its histogram cnt[256] (all
+// threads of the work-group take part): the largest digit d whose keys and
+// those of all higher digits number at least the rank; the rank becomes the
+// rank inside digit d. Suffix sums come from a scan over the digits in
+// descending order (thread t holds digit 255 - t).
+__device__ __forceinline__ void radix_pick(const uint32_t* cnt, SelRadix& r, uint32_t* wsum, int64_t* pick) {
+  const int t = threadIdx.x, d = 255 - t;
+  const uint32_t c = cnt[d];
+  uint32_t total = 0;
+  const uint64_t above = sel_scan(c, wsum, total);   // keys of digits > d
+  const uint64_t upto = above + c;                   // keys of digits >= d
+  if ((int64_t)above < r.rank && ((int64_t)upto >= r.rank || d == 0)) {
+    pick[0] = d;
+    pick[1] = r.rank - (int64_t)above;
+  }
+  __syncthreads();
+  r.prefix = (r.prefix << 8) | (uint64_t)pick[0];
+  r.rank = pick[1];
+  r.shift -= 8;
+  __syncthreads();
+}
+
+// Radix pass `pass`: resolve the previous pass's digit (pass 0: the highest
+// digit in use), then count the next digit of the packed keys whose
+// resolved high bits equal the prefix. Work-group 0 records the selection
+// for the next pass and clears the histogram slot the pass after next
+// adds into (last read by the pass before this one).
+__global__ __launch_bounds__(kSelThreads) void sel_hist_kernel(SelLaunch S, int pass) {
+  __shared__ uint32_t h[256];
+  __shared__ uint32_t wsum[kSelThreads / 64];
+  __shared__ int64_t pick[2];
+  SelRadix r;
+  if (pass == 0) {
+    const SelState st = *S.state;
+    const int bits = st.top ? 64 - __clzll((long long)st.top) : 0;
+    r = SelRadix{0ull, st.k, st.k > 0 ? (bits + 7) / 8 * 8 : 0, 0};
+  } else {
+    r = S.ring[(pass - 1) & 1];
+    if (r.shift > 0) radix_pick(S.hist + ((pass - 1) % 3) * 256, r, wsum, pick);
+  }
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) S.ring[pass & 1] = r;
+    if (pass >= 2) S.hist[((pass + 1) % 3) * 256 + threadIdx.x] = 0;
+  }
+  if (r.shift == 0) return;  // nothing to select, or resolved
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = S.state->candidates;
+  const int shift = r.shift - 8;
+  for (int64_t c = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; c < n; c += (int64_t)gridDim.x * kSelThreads) {
+    const uint64_t key = S.ckeys[c];
+    if (r.shift == 64 || (key >> r.shift) == r.prefix) atomicAdd(&h[(key >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  const uint32_t cnt = h[threadIdx.x];
+  if (cnt) atomicAdd(&S.hist[(pass % 3) * 256 + threadIdx.x], cnt);
 }
 
 __global__ __launch_bounds__(kSelThreads) void sel_mask_kernel(SelLaunch S) {
@@ -246,10 +319,9 @@ hipError_t launch_select(const SelLaunch& S, hipStream_t s) {
   }
   hipLaunchKernelGGL(sel_count_kernel<0>, dim3(grid), dim3(kSelThreads), 0, s, S);
   hipLaunchKernelGGL(sel_scan_kernel<0>, dim3(1), dim3(1024), 0, s, S);
-  for (int pass = 0; pass < 8; ++pass) {
-    hipLaunchKernelGGL(sel_hist_kernel, dim3(grid), dim3(kSelThreads), 0, s, S);
-    hipLaunchKernelGGL(sel_pick_kernel, dim3(1), dim3(256), 0, s, S);
-  }
+  hipLaunchKernelGGL(sel_compact_kernel, dim3(grid), dim3(kSelThreads), 0, s, S);
+  for (int pass = 0; pass < kSelPasses; ++pass)
+    hipLaunchKernelGGL(sel_hist_kernel, dim3(grid), dim3(kSelThreads), 0, s, S, pass);
   hipLaunchKernelGGL(sel_count_kernel<1>, dim3(grid), dim3(kSelThreads), 0, s, S);
   hipLaunchKernelGGL(sel_scan_kernel<1>, dim3(1), dim3(1024), 0, s, S);
   hipLaunchKernelGGL(sel_mask_kernel, dim3(grid), dim3(kSelThreads), 0, s, S);

@@ -91,3 +91,21 @@ def test_split_mask_repeated_calls_and_empty():
     empty = synth.Contributions(*(np.zeros(0, t) for t in (np.int32, np.int32, np.int32, np.float32)))
     run(N, N, W, H, empty, grad, 1e-4, False, N + 700, maps, off)     # all scores 0: index order
     run(0, 16, W, H, c, np.zeros(0, np.float32), 0.0, False, 100, maps, off)   # N = 0
+
+
+@pytest.mark.parametrize("scale", [2e-9, 1.0, 3.0e6])
+def test_split_mask_key_widths(scale):
+    """The radix selection starts at the highest digit any candidate key
+    uses: keys of one byte (scores of a few units of 2^-32), of about 40 bits
+    (the usual range), and of 58-60 bits (the top digit of the 64-bit key)."""
+    N = 6000
+    W, H = [150, 90], [120, 77]
+    maps, off = _maps(11, W, H)
+    maps = (maps * np.float32(scale)).astype(np.float32)
+    c = synth.contributions(12, N, W, H, 3)
+    grad = synth.grad_accum(13, N)
+    ref = oracle.split_scores(maps, W, H, off, c.gauss, c.view, c.pixel, c.weight, N)
+    bits = int(ref.max()).bit_length()
+    assert (scale < 1e-6 and bits <= 8) or (scale == 1.0 and 30 < bits < 48) or (scale > 1e6 and bits > 56), bits
+    for budget in (N + 1, N + 1500, N + 5999):
+        run(N, N + 7, W, H, c, grad, 1e-4, False, budget, maps, off)
