@@ -83,6 +83,18 @@ def _counter_kib(rows, name_part: str, counter: str):
     return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
 
 
+def kernel_part(name: str) -> str:
+    """The part of the hot path a traced kernel belongs to."""
+    parts = (("edge_fused", "edge: fused stencil"), ("edge_persistent", "edge: persistent form"),
+             ("median_", "edge: median"), ("refine_select", "edge: median"), ("normalise", "edge: normalise"),
+             ("uf_", "edge: unfused ablation"), ("las_", "Long-Axis-Split (and full record)"),
+             ("sel_", "split mask"), ("copyBuffer", "runtime copy"), ("Fill", "torch fill"))
+    for key, part in parts:
+        if key in name:
+            return part
+    return "other"
+
+
 def summarise_profile(d: str, copy_bytes: int):
     """Turn the rocprofv3 outputs under directory d (trace/, fetch/, write/,
     copy_fetch/, copy_write/ and bench.json, see the commands recorded in the
@@ -105,13 +117,17 @@ def summarise_profile(d: str, copy_bytes: int):
              " > <dir>/bench.json", "",
              f"Benchmark line of that run: form `{res['config']['form']}`, tile {res['config']['tile']}, "
              f"{res['ms_per_step']} ms/step; live HIP-event time of `{kernel}`: {res['stage_ms']['fused']} ms.", "",
-             "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share |", "|---|---|---|---|---|---|"]
+             "Every kernel of the run (the bench times the graph-captured step, then each further form and row "
+             "on its own: the plain per-view FP32 form is the many small launches), with the part of the hot "
+             "path it belongs to:", "",
+             "| Kernel | Part | Calls | Average (us) | Min (us) | Max (us) | Share |", "|---|---|---|---|---|---|---|"]
     total = sum(float(r["TotalDurationNs"]) for r in stats) or 1.0
-    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:40]:
         nm = r["Name"].replace("igsp::(anonymous namespace)::", "").split("(")[0].replace("void ", "")
         nm = nm if len(nm) < 70 else nm[:67] + "..."
-        lines.append(f"| `{nm}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
-                     f"{float(r['MaxNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / total:.1f}% |")
+        lines.append(f"| `{nm}` | {kernel_part(nm)} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{100 * float(r['TotalDurationNs']) / total:.1f}% |")
     avg = [float(r["AverageNs"]) for r in stats if sym in r["Name"]]
     if avg:
         lines += ["", f"`{kernel}` average over the trace: {avg[0] / 1e6:.4f} ms; the benchmark's live "
@@ -425,7 +441,8 @@ def main():
         select = {"contributions": cb.n, "order": args.contrib_order, "gaussians": N0,
                   "selected": int(snsel.item()), "ms": round(sms, 4),
                   "contributions_per_s": round(cb.n / (sms * 1e-3), 1),
-                  "algorithmic_bytes": int(sbytes), "algorithmic_GBps": round(sbytes / (sms * 1e-3) / 1e9, 1)}
+                  "algorithmic_bytes": int(sbytes), "algorithmic_GBps": round(sbytes / (sms * 1e-3) / 1e9, 1),
+                  "frac_of_hbm_peak": round(sbytes / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"split mask: {sms:.3f} ms, {select['selected']} selected")
         del cg, cv, cp, cw, tg, cb
 
@@ -461,7 +478,8 @@ def main():
         las_full = {"feat_dim": F, "adam_moments": "m and v of all five groups", "ms": round(fms, 4),
                     "gaussians_split_per_s": round(K / (fms * 1e-3), 1),
                     "algorithmic_bytes": int(fbytes),
-                    "algorithmic_GBps": round(fbytes / (fms * 1e-3) / 1e9, 1)}
+                    "algorithmic_GBps": round(fbytes / (fms * 1e-3) / 1e9, 1),
+                    "frac_of_hbm_peak": round(fbytes / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"full-record split: {fms:.3f} ms")
         del Gf, mom, maskf, sidxf
 
@@ -612,7 +630,9 @@ def main():
                       "algorithmic_bytes": int(las_bytes),
                       "algorithmic_GBps": round(las_bytes / (las_ms * 1e-3) / 1e9, 1),
                       "touched_bytes": int(touched),
-                      "touched_GBps": round(touched / (las_ms * 1e-3) / 1e9, 1)}
+                      "touched_GBps": round(touched / (las_ms * 1e-3) / 1e9, 1),
+                      "frac_of_hbm_peak": round(las_bytes / (las_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "touched_frac_of_hbm_peak": round(touched / (las_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if select:
         res["split_mask"] = select
     if las_full:
