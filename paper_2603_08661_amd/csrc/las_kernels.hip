@@ -185,7 +185,9 @@ __device__ __forceinline__ void split_row(const LasLaunch& L, int64_t i, int64_t
 // rows, so their moment rows form one contiguous span, cleared with 16-byte
 // stores; a parent's row of width w is handled by w consecutive lanes, 64 / w
 // rows per wavefront step (the lane's row and element come from divisions
-// done once).
+// done once), each lane moving one float, or one float4 when the row width
+// is a multiple of 4 and the array 16-byte aligned (feature rows and their
+// moments).
 
 // Zero n floats from p (p 4-byte aligned): 16-byte stores in the aligned middle.
 __device__ __forceinline__ void zero_span(float* p, int64_t n) {
@@ -235,38 +237,96 @@ __device__ __forceinline__ void zero_parents(float* a, int w, const RowLanes& rl
   }
 }
 
+// Wide rows (width a multiple of 4 floats, 16-byte aligned array): a lane
+// moves 16 bytes, and each wavefront keeps kWideInFlight rows' loads in
+// flight before their stores (a row-by-row copy waits a full memory latency
+// per row).
+constexpr int kWideInFlight = 4;
+
+__device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// dst row N + first + r = src row base + rows[r] for the tile's r < total
+// (w4 = row width in float4).
+__device__ __forceinline__ void copy_rows4(float4* a, int w4, const int32_t* rows, int64_t base, int64_t dst0,
+                                           int total) {
+  const RowLanes rl = row_lanes(w4);
+  const int wv = threadIdx.x >> 6;
+  constexpr int NWV = kLasThreads / 64;
+  if (rl.rpw > 0) {
+    if (rl.lr < 0) return;
+    const int step = NWV * rl.rpw;
+    for (int r0 = wv * rl.rpw + rl.lr; r0 < total; r0 += step * kWideInFlight) {
+      float4 v[kWideInFlight];
+#pragma unroll
+      for (int u = 0; u < kWideInFlight; ++u) {
+        const int r = r0 + u * step;
+        if (r < total) v[u] = a[(base + rows[r]) * w4 + rl.le];
+      }
+#pragma unroll
+      for (int u = 0; u < kWideInFlight; ++u) {
+        const int r = r0 + u * step;
+        if (r < total) a[(dst0 + r) * w4 + rl.le] = v[u];
+      }
+    }
+  } else {
+    for (int r = wv; r < total; r += NWV)
+      for (int e = rl.le; e < w4; e += 64) a[(dst0 + r) * w4 + e] = a[(base + rows[r]) * w4 + e];
+  }
+}
+
+// The tile's parent rows of a wide array cleared with 16-byte stores.
+__device__ __forceinline__ void zero_parents4(float4* a, int w4, const int32_t* rows, int64_t base, int total) {
+  const RowLanes rl = row_lanes(w4);
+  const int wv = threadIdx.x >> 6;
+  constexpr int NWV = kLasThreads / 64;
+  const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (rl.rpw > 0) {
+    if (rl.lr < 0) return;
+    for (int r = wv * rl.rpw + rl.lr; r < total; r += NWV * rl.rpw) a[(base + rows[r]) * w4 + rl.le] = z;
+  } else {
+    for (int r = wv; r < total; r += NWV)
+      for (int e = rl.le; e < w4; e += 64) a[(base + rows[r]) * w4 + e] = z;
+  }
+}
+
 __device__ __forceinline__ void row_work(const LasLaunch& L, const int32_t* rows, int64_t base, int64_t N,
                                          int64_t first, int total) {
   const int F = L.g.feat_dim;
   const int wv = threadIdx.x >> 6;
   constexpr int NWV = kLasThreads / 64;
+  const bool wideF = F > 0 && (F & 3) == 0;
   if (F > 0) {  // second children's features from the parents
-    const RowLanes rl = row_lanes(F);
     float* f = L.g.features;
-    if (rl.rpw > 0) {
-      if (rl.lr >= 0)
-        for (int r = wv * rl.rpw + rl.lr; r < total; r += NWV * rl.rpw)
-          f[(N + first + r) * F + rl.le] = f[(base + rows[r]) * F + rl.le];
+    if (wideF && aligned16(f)) {
+      copy_rows4(reinterpret_cast<float4*>(f), F / 4, rows, base, N + first, total);
     } else {
-      for (int r = wv; r < total; r += NWV)
-        for (int e = rl.le; e < F; e += 64) f[(N + first + r) * F + e] = f[(base + rows[r]) * F + e];
+      const RowLanes rl = row_lanes(F);
+      if (rl.rpw > 0) {
+        if (rl.lr >= 0)
+          for (int r = wv * rl.rpw + rl.lr; r < total; r += NWV * rl.rpw)
+            f[(N + first + r) * F + rl.le] = f[(base + rows[r]) * F + rl.le];
+      } else {
+        for (int r = wv; r < total; r += NWV)
+          for (int e = rl.le; e < F; e += 64) f[(N + first + r) * F + e] = f[(base + rows[r]) * F + e];
+      }
     }
   }
   const igsp_adam_moments& A = L.adam;
-  float* const arr[5][2] = {{A.means[0], A.means[1]}, {A.log_scales[0], A.log_scales[1]},
-                            {A.quats[0], A.quats[1]}, {A.opacity_logits[0], A.opacity_logits[1]},
-                            {A.features[0], A.features[1]}};
-  const int width[5] = {3, 3, 4, 1, F};
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    if (width[k] == 0 || (!arr[k][0] && !arr[k][1])) continue;
-    const RowLanes rl = row_lanes(width[k]);
+  for (int m = 0; m < 2; ++m) {
+    float* const narrow[4] = {A.means[m], A.log_scales[m], A.quats[m], A.opacity_logits[m]};
+    const int width[4] = {3, 3, 4, 1};
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      float* a = arr[k][m];
-      if (!a) continue;
-      zero_parents(a, width[k], rl, rows, base, total);
-      zero_span(a + (N + first) * width[k], (int64_t)total * width[k]);
+    for (int k = 0; k < 4; ++k)
+      if (narrow[k]) {
+        zero_parents(narrow[k], width[k], row_lanes(width[k]), rows, base, total);
+        zero_span(narrow[k] + (N + first) * width[k], (int64_t)total * width[k]);
+      }
+    float* const fm = F > 0 ? A.features[m] : nullptr;
+    if (fm) {
+      if (wideF && aligned16(fm)) zero_parents4(reinterpret_cast<float4*>(fm), F / 4, rows, base, total);
+      else zero_parents(fm, F, row_lanes(F), rows, base, total);
+      zero_span(fm + (N + first) * F, (int64_t)total * F);
     }
   }
 }

@@ -181,9 +181,10 @@ def test_two_calls_grow_count_on_device():
     assert np.abs(res["means"][:1200] - r2["means"][:1200]).max() < 1e-5
 
 
-def _run_full(g, N, mask, cap, F, seed, groups, over_capacity=False):
+def _run_full(g, N, mask, cap, F, seed, groups, over_capacity=False, misalign=False):
     """long_axis_split_full with F feature floats and random moments for the
-    given groups; returns (result dict as run_las, moments before, after)."""
+    given groups; returns (result dict as run_las, moments before, after).
+    misalign: every array starts 4 bytes past a 16-byte boundary."""
     import torch
 
     import paper_2603_08661_amd as igsp
@@ -201,10 +202,19 @@ def _run_full(g, N, mask, cap, F, seed, groups, over_capacity=False):
     host = {"means": padded(g.means, cap), "log_scales": padded(g.log_scales, cap),
             "quats": padded(g.quats, cap), "opacity_logits": padded(g.opacity_logits, cap),
             "features": padded(feats, cap)}
-    t = {k: torch.from_numpy(v.copy()).to(dev) for k, v in host.items()}
+    def dev_array(a):
+        if not misalign:
+            return torch.from_numpy(a.copy()).to(dev)
+        flat = torch.zeros(a.size + 1, dtype=torch.float32, device=dev)
+        view = flat[1:].view(a.shape)
+        view.copy_(torch.from_numpy(a))
+        assert view.data_ptr() % 16 == 4
+        return view
+
+    t = {k: dev_array(v) for k, v in host.items()}
     mom_host = {grp: [rng.normal(size=(cap, widths[grp])).astype(np.float32).squeeze(-1 if widths[grp] == 1 else ())
                       for _ in range(2)] for grp in groups}
-    mom = {grp: tuple(torch.from_numpy(a.copy()).to(dev) for a in pair) for grp, pair in mom_host.items()}
+    mom = {grp: tuple(dev_array(a) for a in pair) for grp, pair in mom_host.items()}
     count = torch.tensor([N], dtype=torch.int64, device=dev)
     mk = np.zeros(cap, np.uint8)
     mk[:N] = mask[:N]
@@ -227,6 +237,8 @@ def _run_full(g, N, mask, cap, F, seed, groups, over_capacity=False):
     (70001, 9000, 48, ("means", "opacity_logits", "features")),
     (2049, 2049, 3, ("log_scales", "features")),
     (5000, 0, 48, ("means", "features")),
+    (9000, 2500, 8, ("means", "log_scales", "quats", "opacity_logits", "features")),   # 32 rows per wave step
+    (3000, 900, 260, ("quats", "features")),    # a row wider than a wavefront of 16-byte lanes
 ])
 def test_full_record_split(N, K, F, groups):
     g = synth.gaussians(21, N)
@@ -240,6 +252,22 @@ def test_full_record_split(N, K, F, groups):
             assert (after[grp][k] == want).all(), (grp, k)
     # canary rows past N + K keep the parameters' canary and their moments
     assert (res["features"][N + K:] == CANARY).all()
+
+
+@pytest.mark.parametrize("N,K,F", [(6000, 1500, 48), (4100, 300, 8)])
+def test_full_record_split_unaligned_arrays(N, K, F):
+    """Arrays that do not start on a 16-byte boundary take the row-by-row
+    paths (dense tiles and sparse tiles alike) with the same results."""
+    groups = ("means", "log_scales", "quats", "opacity_logits", "features")
+    g = synth.gaussians(27, N)
+    mk = synth.mask(28, N, K)
+    cap = N + K + 9
+    res, before, after = _run_full(g, N, mk, cap, F, 29, groups, misalign=True)
+    ref = compare(res, N, cap, feats=res["host"]["features"])
+    for grp in groups:
+        for k in range(2):
+            want = oracle.las_moments(N, ref["split_idx"], {"x": before[grp][k]})["x"]
+            assert (after[grp][k] == want).all(), (grp, k)
 
 
 def test_full_record_split_capacity_overflow_touches_nothing():
