@@ -183,11 +183,11 @@ __device__ __forceinline__ void split_row(const LasLaunch& L, int64_t i, int64_t
 // children's feature rows copied from the parents, and the given moment rows
 // of both children cleared. The second children of a tile are consecutive
 // rows, so their moment rows form one contiguous span, cleared with 16-byte
-// stores; a parent's row of width w is handled by w consecutive lanes, 64 / w
-// rows per wavefront step (the lane's row and element come from divisions
-// done once), each lane moving one float, or one float4 when the row width
-// is a multiple of 4 and the array 16-byte aligned (feature rows and their
-// moments).
+// stores. A parent's moment row of at most 4 floats is cleared by one lane;
+// a wider row (features, their moments) by consecutive lanes, 64 / w rows per
+// wavefront step (the lane's row and element come from divisions done once),
+// each lane moving one float, or one float4 when the row width is a
+// multiple of 4 and the array 16-byte aligned.
 
 // Zero n floats from p (p 4-byte aligned): 16-byte stores in the aligned middle.
 __device__ __forceinline__ void zero_span(float* p, int64_t n) {
@@ -289,6 +289,16 @@ __device__ __forceinline__ void zero_parents4(float4* a, int w4, const int32_t* 
   }
 }
 
+// Narrow parent rows (W <= 4 floats) cleared one row per lane.
+template <int W>
+__device__ __forceinline__ void zero_parents_rows(float* a, const int32_t* rows, int64_t base, int total) {
+  for (int r = threadIdx.x; r < total; r += kLasThreads) {
+    float* p = a + (base + rows[r]) * W;
+#pragma unroll
+    for (int j = 0; j < W; ++j) p[j] = 0.0f;
+  }
+}
+
 __device__ __forceinline__ void row_work(const LasLaunch& L, const int32_t* rows, int64_t base, int64_t N,
                                          int64_t first, int total) {
   const int F = L.g.feat_dim;
@@ -316,12 +326,13 @@ __device__ __forceinline__ void row_work(const LasLaunch& L, const int32_t* rows
   for (int m = 0; m < 2; ++m) {
     float* const narrow[4] = {A.means[m], A.log_scales[m], A.quats[m], A.opacity_logits[m]};
     const int width[4] = {3, 3, 4, 1};
+    if (narrow[0]) zero_parents_rows<3>(narrow[0], rows, base, total);
+    if (narrow[1]) zero_parents_rows<3>(narrow[1], rows, base, total);
+    if (narrow[2]) zero_parents_rows<4>(narrow[2], rows, base, total);
+    if (narrow[3]) zero_parents_rows<1>(narrow[3], rows, base, total);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (narrow[k]) {
-        zero_parents(narrow[k], width[k], row_lanes(width[k]), rows, base, total);
-        zero_span(narrow[k] + (N + first) * width[k], (int64_t)total * width[k]);
-      }
+      if (narrow[k]) zero_span(narrow[k] + (N + first) * width[k], (int64_t)total * width[k]);
     float* const fm = F > 0 ? A.features[m] : nullptr;
     if (fm) {
       if (wideF && aligned16(fm)) zero_parents4(reinterpret_cast<float4*>(fm), F / 4, rows, base, total);
