@@ -50,6 +50,20 @@ def test_tile_shapes(seg_rows, wg_waves, form):
     check_batch(vb, "fp32", form, seg_rows=seg_rows, wg_waves=wg_waves)
 
 
+@pytest.mark.parametrize("precision", PRECS)
+def test_random_view_sizes(precision):
+    """48 views of seeded random sizes, from 3x3 up to several strips wide
+    and bands tall, at random alignments: many short last bands in the
+    launch's per-XCD order, every border case of the strips."""
+    rng = np.random.default_rng(2024)
+    sizes = [(int(rng.integers(3, 700)), int(rng.integers(3, 260))) for _ in range(48)]
+    imgs = [synth.image(500 + k, w, h, n_poly=5, texture=bool(k % 2)) for k, (w, h) in enumerate(sizes)]
+    vb = synth.pack_views(imgs, in_align=int(rng.integers(1, 17)), out_align=int(rng.integers(1, 5)))
+    for form, kw in (("staged", {}), ("staged", {"seg_rows": 16, "wg_waves": 2}), ("plain", {})):
+        st = check_batch(vb, precision, form, **kw)
+        print(precision, form, kw, sum(s["mismatch"] for s in st), max(s["scaled_err"] for s in st))
+
+
 def test_adversarial_images():
     H, W = 40, 300
     imgs = []
