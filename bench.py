@@ -616,6 +616,11 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roof,
         "copy_ceiling_GBps": round(copy_gbps, 1),
+        "normalise": {"ms": round(stage_ms["normalise"], 4),
+                      "algorithmic_bytes": int(vb.pixels * (sb + 4)),
+                      "algorithmic_GBps": round(vb.pixels * (sb + 4) / (stage_ms["normalise"] * 1e-3) / 1e9, 1),
+                      "frac_of_hbm_peak": round(vb.pixels * (sb + 4) / (stage_ms["normalise"] * 1e-3) / 1e9
+                                                / HBM_PEAK_GBS, 4)} if stage_ms.get("normalise", 0) > 0.01 else None,
         "edge_pipeline": {"ms": round(stage_ms["edge"], 4),
                           "mpx_per_s": round(mpx / (stage_ms["edge"] * 1e-3), 1),
                           "algorithmic_GBps": round(vb.pixels * 7 / (stage_ms["edge"] * 1e-3) / 1e9, 1),
