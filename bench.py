@@ -261,11 +261,13 @@ def profile_facts(kernel: str, prec: str, workload: str, seg_rows: int, wg_waves
 
 
 def main():
+    import synth
+
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=5, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--workload", default="step_views300_las3m", choices=sorted(synth.WORKLOADS))
     ap.add_argument("--precision", default=None, help="override the workload's intermediate storage")
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--wg-waves", type=int, default=0)
@@ -305,14 +307,13 @@ def main():
     import torch
 
     import paper_2603_08661_amd as igsp
-    import synth
 
     dev = torch.device("cuda:0")
     w = synth.workload(args.workload)
     prec = args.precision or w.precision
     t0 = time.time()
     vb = w.render()
-    log(f"workload {w.index}: {vb.n} views, {vb.pixels / 1e6:.1f} MPx rendered in {time.time() - t0:.1f}s")
+    log(f"workload {args.workload}: {vb.n} views, {vb.pixels / 1e6:.1f} MPx rendered in {time.time() - t0:.1f}s")
     img = torch.from_numpy(np.concatenate([vb.rgb, np.zeros(16, np.uint8)])).to(dev)
     out = torch.zeros(vb.out_floats, dtype=torch.float32, device=dev)
     views = (vb.widths, vb.heights, vb.in_offset, vb.out_offset)
@@ -422,8 +423,8 @@ def main():
     select = None
     if has_las and not args.no_select:
         t1 = time.time()
-        cb = synth.contributions(7000001 * w.index + 2, N0, vb.widths, vb.heights, 3, order=args.contrib_order)
-        gr = synth.grad_accum(7000001 * w.index + 3, N0)
+        cb = synth.contributions(7000001 * w.stream + 2, N0, vb.widths, vb.heights, 3, order=args.contrib_order)
+        gr = synth.grad_accum(7000001 * w.stream + 3, N0)
         thr = float(np.quantile(gr, 0.6))          # 40% of the Gaussians pass the gradient test
         log(f"contributions: {cb.n} entries ({time.time() - t1:.1f}s)")
         T = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731

@@ -227,8 +227,8 @@ def grad_accum(seed: int, n: int) -> np.ndarray:
 
 @dataclass
 class Workload:
-    """One of the five named workloads: views to render plus a Gaussian set."""
-    index: int
+    """One of the named workloads: views to render plus a Gaussian set."""
+    stream: int               # seed stream of the workload's inputs
     name: str
     seeds: np.ndarray
     full_w: np.ndarray
@@ -269,14 +269,28 @@ class Workload:
                      n_poly=self.n_poly, texture=self.texture, **kw)
 
     def gaussian_set(self) -> GaussianSet:
-        return gaussians(7000001 * self.index, self.n_gauss, self.ls_mu, self.ls_sd)
+        return gaussians(7000001 * self.stream, self.n_gauss, self.ls_mu, self.ls_sd)
 
     def split_mask(self) -> np.ndarray:
-        return mask(7000001 * self.index + 1, self.n_gauss, self.n_split)
+        return mask(7000001 * self.stream + 1, self.n_gauss, self.n_split)
 
 
-def workload(c: int) -> Workload:
-    """The five named workloads, numbered 1..5."""
+# The workloads by name; the value is each one's seed stream.
+WORKLOADS = {
+    "view_256x192": 1,
+    "view_1297x840": 2,
+    "views200_w1000_1560": 3,
+    "views150_2473x1643_mixed": 4,
+    "step_views300_las3m": 5,
+}
+
+
+def workload(key: str) -> Workload:
+    """The named workload `key` (one of WORKLOADS)."""
+    if key not in WORKLOADS:
+        raise ValueError(f"unknown workload {key!r}; one of {sorted(WORKLOADS)}")
+    c = WORKLOADS[key]
+
     def seeds(n):
         return np.array([1000003 * c + v for v in range(n)], np.uint64)
 
@@ -305,4 +319,4 @@ def workload(c: int) -> Workload:
         return Workload(5, "densification step: 300 views W in [1000,2473] bf16 + LAS 3M Gaussians, 20% split",
                         seeds(300), W, H, np.zeros(300, np.int32), 60, True, "bf16", True,
                         3_000_000, -4.5, 0.7, 0.20, graph=True)
-    raise ValueError(f"unknown workload {c}")
+    raise AssertionError(c)

@@ -27,8 +27,8 @@ def small_batch(in_align=1, out_align=1):
 
 
 @pytest.mark.parametrize("precision", PRECS)
-def test_workload1_single_view(precision):
-    w = synth.workload(1)
+def test_single_256x192_view(precision):
+    w = synth.workload("view_256x192")
     vb = w.render(in_align=256, out_align=64)
     for form in ("plain", "staged", "persistent"):
         st = check_batch(vb, precision, form)
@@ -118,29 +118,29 @@ def test_permuting_views_permutes_outputs():
         assert (view_map(a, vb, v) == view_map(b, vp, k)).all()
 
 
-def test_workload2_full_oracle():
-    w = synth.workload(2)
+def test_single_1297x840_view_full_oracle():
+    w = synth.workload("view_1297x840")
     vb = w.render(in_align=256, out_align=64)
     for p, form in zip(PRECS, ("plain", "staged", "persistent")):
         st = check_batch(vb, p, form)
-        print("workload2", p, form, st)
+        print(w.name, p, form, st)
 
 
-@pytest.mark.parametrize("c,precisions,sample", [(3, ["fp16", "fp32"], [0, 57, 199]),
-                                                 (4, ["fp16", "bf16"], [0, 1, 148, 149]),
-                                                 (5, ["bf16"], [0, 150, 299])])
-def test_full_size_workloads_sampled(c, precisions, sample):
+@pytest.mark.parametrize("name,precisions,sample", [("views200_w1000_1560", ["fp16", "fp32"], [0, 57, 199]),
+                                                    ("views150_2473x1643_mixed", ["fp16", "bf16"], [0, 1, 148, 149]),
+                                                    ("step_views300_las3m", ["bf16"], [0, 150, 299])])
+def test_full_size_workloads_sampled(name, precisions, sample):
     """Every view of the full workload goes through one persistent launch (the
     form the benchmark times); sampled views are checked against the oracle
     pixel by pixel, and the staged form must give the same bits."""
-    w = synth.workload(c)
+    w = synth.workload(name)
     vb = w.render()
     refs = {v: oracle.edge_view(vb.view(v)) for v in sample}
     for p in precisions:
         E, med, nsv = gpu_edge(vb, p, "persistent")
         for v in sample:
             st = compare_view(view_map(E, vb, v), refs[v], p, med[v], nsv[v])
-            print(f"workload{c} {p} view {v}", st)
+            print(f"{name} {p} view {v}", st)
         assert (nsv > 0).all() and (med > 0).all()
         E2, med2, nsv2 = gpu_edge(vb, p, "staged")
         assert (E2 == E).all() and (med2 == med).all() and (nsv2 == nsv).all()

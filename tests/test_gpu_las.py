@@ -97,9 +97,9 @@ def compare(res, N, cap, feats=None, **prm):
     return ref
 
 
-@pytest.mark.parametrize("c", [1, 2, 5])
-def test_workloads(c):
-    w = synth.workload(c)
+@pytest.mark.parametrize("name", ["view_256x192", "view_1297x840", "step_views300_las3m"])
+def test_workloads(name):
+    w = synth.workload(name)
     g = w.gaussian_set()
     mk = w.split_mask()
     N = w.n_gauss

@@ -246,7 +246,7 @@ def test_median_is_lower_median_of_survivors(seed, H, W):
 
 
 def test_batch_equals_single_views_any_threads():
-    w = synth.workload(3)
+    w = synth.workload("views200_w1000_1560")
     vb = w.render(views=[0, 1], in_align=1, out_align=1)
     # shrink to keep the test fast: crop two small views
     imgs = [vb.view(0)[:60, :81], vb.view(1)[:33, :47]]

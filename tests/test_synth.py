@@ -26,7 +26,7 @@ def test_noise_statistics():
 
 
 def test_batch_matches_single_and_offsets():
-    w = synth.workload(3)
+    w = synth.workload("views200_w1000_1560")
     vb = w.render(views=[0, 1, 2])
     for k, v in enumerate([0, 1, 2]):
         ref = synth.image(int(w.seeds[v]), int(w.full_w[v]), int(w.full_h[v]), w.n_poly, w.texture)
@@ -35,19 +35,19 @@ def test_batch_matches_single_and_offsets():
 
 
 def test_down2_sizes():
-    w = synth.workload(4)
+    w = synth.workload("views150_2473x1643_mixed")
     Wd, Hd = w.sizes()
     assert set(zip(Wd.tolist(), Hd.tolist())) == {(2473, 1643), (1236, 821)}
     assert int((w.down2 != 0).sum()) == 75
 
 
 def test_view_size_ranges():
-    w = synth.workload(3)
+    w = synth.workload("views200_w1000_1560")
     W, H = w.sizes()
     assert W.min() >= 1000 and W.max() <= 1560
     asp = W / H
     assert asp.min() > 1.49 and asp.max() < 1.78
-    w5 = synth.workload(5)
+    w5 = synth.workload("step_views300_las3m")
     W5, _ = w5.sizes()
     assert W5.min() >= 1000 and W5.max() <= 2473 and w5.n_views == 300
 
