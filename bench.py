@@ -184,6 +184,33 @@ def summarise_profile(d: str, copy_bytes: int):
          "    python3 bench.py --summarise-profile <dir>",
          "  FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by copy_bytes / (1024 x what the same",
          "  counter reads for the plain copy of copy_bytes bytes). traffic = scaled fetch + scaled write."]
+    # the other kernels of the step and of the split-mask row, from the same passes
+    if None not in (f_fetch, f_write):
+        fetch_rows = _csv_rows(os.path.join(d, "fetch", "**", "*counter_collection.csv"))
+        write_rows = _csv_rows(os.path.join(d, "write", "**", "*counter_collection.csv"))
+        npx = res["config"]["megapixels"] * 1e6
+        alg = {f"normalise_kernel<{prec_code}>": npx * (STORE_BYTES[res["config"]["intermediate"]] + 4)}
+        t += ["", "Other kernels, same passes and scaling (MB per dispatch; algorithmic bytes where the "
+                  "benchmark states them per kernel). The split's count grows from step to step; "
+                  "`las_split_kernel` runs both the plain split and the full-record split (feature rows and "
+                  "moments), hence its range:", "",
+              "| Kernel | Dispatches | Fetch | Write | Traffic | Algorithmic |", "|---|---|---|---|---|---|"]
+        for k in (f"normalise_kernel<{prec_code}>", f"median_select_kernel<{prec_code}>", "las_count_kernel",
+                  "las_scan_kernel", "las_split_kernel", "sel_scatter_kernel", "sel_compact_kernel",
+                  "sel_hist_kernel", "sel_mask_kernel"):
+            fv = [float(r["Counter_Value"]) * 1024 * f_fetch for r in fetch_rows
+                  if k in r["Kernel_Name"] and r["Counter_Name"] == "FETCH_SIZE"]
+            wv = [float(r["Counter_Value"]) * 1024 * f_write for r in write_rows
+                  if k in r["Kernel_Name"] and r["Counter_Name"] == "WRITE_SIZE"]
+            if not fv or len(fv) != len(wv):
+                continue
+            tv = [x + y for x, y in zip(fv, wv)]
+
+            def span(v):  # one figure, or the range where dispatches differ (several rows of the bench)
+                lo, hi = min(v) / 1e6, max(v) / 1e6
+                return f"{lo:.1f}" if hi - lo <= max(0.05 * hi, 0.05) else f"{lo:.1f}-{hi:.1f}"
+            a_b = f"{alg[k] / 1e6:.1f}" if k in alg else "-"
+            t.append(f"| `{k}` | {len(fv)} | {span(fv)} | {span(wv)} | {span(tv)} | {a_b} |")
     open(os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic.txt"), "w").write("\n".join(t) + "\n")
     print(json.dumps({"kernel": kernel, "traffic_bytes_per_launch": traffic, "trace_avg_ms":
                       avg[0] / 1e6 if avg else None, "live_ms": res["stage_ms"]["fused"]}))
