@@ -245,12 +245,12 @@ def cpu_model() -> str:
 
 
 def kernel_source_digest() -> str:
-    """SHA-256 over the stencil kernels and the host code that orders their
+    """SHA-256 over the kernel sources and the host code that orders their
     work-groups: counters taken on other sources do not describe this build."""
     import hashlib
 
     h = hashlib.sha256()
-    for name in ("edge_kernels.hip", "igsp_api.hip"):
+    for name in ("edge_kernels.hip", "select_kernels.hip", "las_kernels.hip", "igsp_api.hip", "igsp_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2603_08661_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 

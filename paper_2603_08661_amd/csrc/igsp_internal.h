@@ -194,7 +194,7 @@ hipError_t launch_las(const LasLaunch& L, hipStream_t s);
 constexpr int kSelThreads = 256;
 constexpr int kSelTile = 2048;         // rows per tile of the count / mask kernels
 constexpr int kSelGrid = 1024;         // work-groups of the grid-stride kernels
-constexpr int kSelScatterGrid = 8192;  // work-groups of the contribution scatter
+constexpr int kSelScatterGrid = 2048;  // work-groups of the contribution scatter (8 waves per SIMD)
 
 struct SelView {
   int64_t out_offset;  // floats from `maps`

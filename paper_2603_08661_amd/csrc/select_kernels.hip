@@ -5,10 +5,12 @@
 //   sel_clear   : scores[0, N) = 0, the radix histograms and the key OR = 0
 //                 (fill kernels, so the call can be captured)
 //   sel_scatter : per contribution (Gaussian g, view v, pixel p, weight w):
-//                 scores[g] += floor(fl32(E_v[p] * w) * 2^32), runs of equal
-//                 g on consecutive lanes summed first, then 64-bit atomics;
-//                 fixed point makes the sum exact and independent of the
-//                 order the additions land in
+//                 scores[g] += floor(fl32(E_v[p] * w) * 2^32); each
+//                 work-group sums a chunk of the contributions per Gaussian
+//                 (runs on consecutive lanes, then an LDS hash table) and
+//                 adds each sum with one 64-bit atomic; fixed
+//                 point makes the sum exact and independent of the order
+//                 the additions land in
 //   sel_count<0> / sel_scan<0> : candidates (warm-up, or grad[g] >=
 //                 threshold) per tile, their offsets, and
 //                 K = min(candidates, max(0, budget - N))
@@ -51,38 +53,83 @@ __global__ __launch_bounds__(kSelThreads) void sel_clear_kernel(SelLaunch S) {
 }
 
 // Contributions arrive in image order, so neighbouring entries often name the
-// same Gaussian: each wavefront first sums the runs of equal Gaussian index on
-// consecutive lanes (a segmented suffix sum over the lanes), and only a run's
-// first lane issues the 64-bit atomic.
+// same Gaussian, and a Gaussian's entries recur a few image rows later. The
+// grid sweeps the list in order, one chunk of kScatterRounds x kSelThreads
+// contributions per work-group at a time (so the map reads of neighbouring
+// chunks stay close). Each wavefront first sums the runs of equal Gaussian
+// index on consecutive lanes (a segmented suffix sum over the lanes); a run's
+// first lane then adds the run's sum into the work-group's LDS hash table
+// (open addressing, kScatterProbes linear probes; a run that finds no slot
+// goes straight to its global atomic); at the end of the chunk every used
+// slot issues one 64-bit atomic and is cleared.
+constexpr int kScatterRounds = 16;
+constexpr int kScatterSlots = 1024;  // 12 KB of LDS: keys and 64-bit sums
+constexpr int kScatterProbes = 16;
+static_assert(kScatterSlots == 1 << 10, "the slot hash keeps the top 10 bits");
+
 __global__ __launch_bounds__(kSelThreads) void sel_scatter_kernel(SelLaunch S) {
+  __shared__ int32_t keys[kScatterSlots];
+  __shared__ unsigned long long sums[kScatterSlots];
+  constexpr int64_t kChunk = (int64_t)kScatterRounds * kSelThreads;
   const int64_t N = live_count(S);
   const int lane = threadIdx.x & 63;
-  for (int64_t c0 = (int64_t)blockIdx.x * kSelThreads; c0 < S.n_contrib; c0 += (int64_t)gridDim.x * kSelThreads) {
-    const int64_t c = c0 + threadIdx.x;
-    int32_t g = -1;
-    uint64_t q = 0;
-    if (c < S.n_contrib) {
-      const int32_t gi = S.gauss[c], v = S.view[c], p = S.pixel[c];
-      if (gi >= 0 && gi < N && v >= 0 && v < S.n_views) {             // else outside the live set: ignored
-        const SelView sv = S.views[v];
-        if (p >= 0 && (int64_t)p < sv.pixels) {
-          g = gi;
-          const float e = S.maps[sv.out_offset + p] * S.weight[c];   // one FP32 product
-          if (e > 0.0f) q = (uint64_t)floor((double)e * 4294967296.0);  // exact: fl32 times 2^32
+  for (int i = threadIdx.x; i < kScatterSlots; i += kSelThreads) {
+    keys[i] = -1;
+    sums[i] = 0ull;
+  }
+  __syncthreads();
+  for (int64_t b0 = (int64_t)blockIdx.x * kChunk; b0 < S.n_contrib; b0 += (int64_t)gridDim.x * kChunk) {
+    const int64_t b1 = b0 + kChunk < S.n_contrib ? b0 + kChunk : S.n_contrib;
+    for (int64_t c0 = b0; c0 < b1; c0 += kSelThreads) {
+      const int64_t c = c0 + threadIdx.x;
+      int32_t g = -1;
+      uint64_t q = 0;
+      if (c < b1) {
+        const int32_t gi = S.gauss[c], v = S.view[c], p = S.pixel[c];
+        if (gi >= 0 && gi < N && v >= 0 && v < S.n_views) {             // else outside the live set: ignored
+          const SelView sv = S.views[v];
+          if (p >= 0 && (int64_t)p < sv.pixels) {
+            g = gi;
+            const float e = S.maps[sv.out_offset + p] * S.weight[c];   // one FP32 product
+            if (e > 0.0f) q = (uint64_t)floor((double)e * 4294967296.0);  // exact: fl32 times 2^32
+          }
         }
       }
-    }
-    const int32_t gp = __shfl_up(g, 1, 64);
-    const bool head = lane == 0 || gp != g;
-    const uint64_t heads = __ballot(head);
-    const int rid = __popcll(heads & ((2ull << lane) - 1ull));        // run of this lane
+      const int32_t gp = __shfl_up(g, 1, 64);
+      const bool head = lane == 0 || gp != g;
+      const uint64_t heads = __ballot(head);
+      const int rid = __popcll(heads & ((2ull << lane) - 1ull));        // run of this lane
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint64_t qo = __shfl_down(q, o, 64);
-      const int ro = __shfl_down(rid, o, 64);
-      if (lane + o < 64 && ro == rid) q += qo;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t qo = __shfl_down(q, o, 64);
+        const int ro = __shfl_down(rid, o, 64);
+        if (lane + o < 64 && ro == rid) q += qo;
+      }
+      if (head && g >= 0 && q != 0) {
+        uint32_t h = ((uint32_t)g * 2654435761u) >> (32 - 10);         // 10 bits: kScatterSlots
+        bool placed = false;
+        for (int k = 0; k < kScatterProbes && !placed; ++k) {
+          const int32_t prev = atomicCAS(&keys[h], -1, g);
+          if (prev == -1 || prev == g) {
+            atomicAdd(&sums[h], (unsigned long long)q);
+            placed = true;
+          }
+          h = (h + 1) & (kScatterSlots - 1);
+        }
+        if (!placed) atomicAdd(reinterpret_cast<unsigned long long*>(S.scores + g), (unsigned long long)q);
+      }
     }
-    if (head && g >= 0 && q != 0) atomicAdd(reinterpret_cast<unsigned long long*>(S.scores + g), (unsigned long long)q);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kScatterSlots; i += kSelThreads) {
+      const int32_t g = keys[i];
+      if (g >= 0) {
+        const unsigned long long q = sums[i];
+        if (q != 0ull) atomicAdd(reinterpret_cast<unsigned long long*>(S.scores + g), q);
+        keys[i] = -1;
+        sums[i] = 0ull;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -313,8 +360,8 @@ hipError_t launch_select(const SelLaunch& S, hipStream_t s) {
   const int grid = S.grid;
   hipLaunchKernelGGL(sel_clear_kernel, dim3(grid), dim3(kSelThreads), 0, s, S);
   if (S.n_contrib > 0) {
-    const int64_t cg = (S.n_contrib + kSelThreads - 1) / kSelThreads;
-    hipLaunchKernelGGL(sel_scatter_kernel, dim3((unsigned)(cg < kSelScatterGrid ? cg : kSelScatterGrid)),
+    const int64_t chunks = (S.n_contrib + kScatterRounds * kSelThreads - 1) / (kScatterRounds * kSelThreads);
+    hipLaunchKernelGGL(sel_scatter_kernel, dim3((unsigned)(chunks < kSelScatterGrid ? chunks : kSelScatterGrid)),
                        dim3(kSelThreads), 0, s, S);
   }
   hipLaunchKernelGGL(sel_count_kernel<0>, dim3(grid), dim3(kSelThreads), 0, s, S);
