@@ -20,7 +20,7 @@
 namespace igsp {
 namespace {
 
-constexpr int kFlatChunk = 16384;  // pixels per work-group of the element-wise passes
+constexpr int kFlatChunk = 4096;  // pixels per work-group of the element-wise passes (measured best)
 constexpr int kPersistChunk = 65536;  // pixels per element-wise task of the persistent form
 // Distance, in tasks, between a view's phases in the persistent task list, as
 // a multiple of the resident work-groups: a task handed out that many
