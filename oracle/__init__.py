@@ -50,6 +50,8 @@ def lib():
         L.orc_blur_taps.restype = None
         L.orc_bin.argtypes = [i64, i64]
         L.orc_bin.restype = i32
+        L.orc_nms.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp]
+        L.orc_nms.restype = None
         L.orc_edge_view.argtypes = [vp, i32, i32] + [vp] * 12
         L.orc_edge_view.restype = i64
         L.orc_edge_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32]
@@ -78,6 +80,23 @@ def blur_taps() -> np.ndarray:
 def bin_of(gx: int, gy: int) -> int:
     """Orientation bin: 0 horizontal, 1 vertical, 2 diagonal gx*gy>0, 3 otherwise."""
     return int(lib().orc_bin(int(gx), int(gy)))
+
+
+def nms(gx: np.ndarray, gy: np.ndarray) -> dict:
+    """Suppression step alone (Sec. 2.1 step 3) on a given integer gradient
+    field (H, W): squared magnitude M, orientation bin, keep, and the
+    decision margin c(p)."""
+    gx = np.ascontiguousarray(gx, np.int64)
+    gy = np.ascontiguousarray(gy, np.int64)
+    if gx.shape != gy.shape or gx.ndim != 2:
+        raise ValueError("gx and gy must be 2-D arrays of one shape")
+    H, W = gx.shape
+    if W < 3 or H < 3:
+        raise ValueError("fields must be at least 3x3")
+    o = {"M": np.zeros((H, W), np.int64), "bin": np.zeros((H, W), np.uint8),
+         "keep": np.zeros((H, W), np.uint8), "margin": np.zeros((H, W), np.float64)}
+    lib().orc_nms(_p(gx), _p(gy), W, H, _p(o["M"]), _p(o["bin"]), _p(o["keep"]), _p(o["margin"]))
+    return o
 
 
 def edge_view(rgb: np.ndarray) -> dict:

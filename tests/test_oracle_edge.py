@@ -268,19 +268,18 @@ def test_rejects_views_below_3x3():
 
 # ---------------------------------------------------------------- exact brute force, whole pipeline
 
-def _brute_pipeline(im):
-    """Every step of Sec. 2.1 in plain Python integers on a small image, with
-    formulations that differ from the oracle's: explicit reflect-101 by
-    repeated mirroring, the 5x5 blur as one 25-term sum, the orientation from
-    the exact comparison (|gx| + |gy|)^2 vs 2 g^2, the median by sorting.
-    Returns (keep, M, M of the median survivor or None)."""
+def _brute_refl(i, n):
+    """Reflect-101 by repeated mirroring about the border pixels."""
+    while i < 0 or i >= n:
+        i = -i if i < 0 else 2 * (n - 1) - i
+    return i
+
+
+def _brute_gradients(im):
+    """Gray, the 5x5 blur as one 25-term sum and the Sobel pair, in plain
+    Python integers with explicit reflect-101. Returns (gx, gy) as lists."""
     H, W = im.shape[:2]
-
-    def refl(i, n):
-        while i < 0 or i >= n:
-            i = -i if i < 0 else 2 * (n - 1) - i
-        return i
-
+    refl = _brute_refl
     g = [[299 * int(im[y, x, 0]) + 587 * int(im[y, x, 1]) + 114 * int(im[y, x, 2]) for x in range(W)]
          for y in range(H)]
     w = [1, 4, 6, 4, 1]
@@ -294,6 +293,18 @@ def _brute_pipeline(im):
           for y in range(H)]
     gy = [[sum(c * (B(y + 1, x + dx) - B(y - 1, x + dx)) for dx, c in ((-1, 1), (0, 2), (1, 1))) for x in range(W)]
           for y in range(H)]
+    return gx, gy
+
+
+def _brute_pipeline(im):
+    """Every step of Sec. 2.1 in plain Python integers on a small image, with
+    formulations that differ from the oracle's: explicit reflect-101 by
+    repeated mirroring, the 5x5 blur as one 25-term sum, the orientation from
+    the exact comparison (|gx| + |gy|)^2 vs 2 g^2, the median by sorting.
+    Returns (keep, M, M of the median survivor or None)."""
+    H, W = im.shape[:2]
+    refl = _brute_refl
+    gx, gy = _brute_gradients(im)
     M = [[gx[y][x] ** 2 + gy[y][x] ** 2 for x in range(W)] for y in range(H)]
 
     def sgn(v):
