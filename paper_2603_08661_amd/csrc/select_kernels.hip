@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kSelThreads) void sel_scatter_kernel(SelLaunch S) {
           if (p >= 0 && (int64_t)p < sv.pixels) {
             g = gi;
             const float e = S.maps[sv.out_offset + p] * S.weight[c];   // one FP32 product
-            if (e > 0.0f) q = (uint64_t)floor((double)e * 4294967296.0);  // exact: fl32 times 2^32
+            if (e > 0.0f) q = (uint64_t)floorf(e * 4294967296.0f);       // exact: a power-of-two scale
           }
         }
       }

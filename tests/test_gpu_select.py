@@ -109,3 +109,30 @@ def test_split_mask_key_widths(scale):
     assert (scale < 1e-6 and bits <= 8) or (scale == 1.0 and 30 < bits < 48) or (scale > 1e6 and bits > 56), bits
     for budget in (N + 1, N + 1500, N + 5999):
         run(N, N + 7, W, H, c, grad, 1e-4, False, budget, maps, off)
+
+
+@pytest.mark.parametrize("order", ["rows", "spread"])
+@pytest.mark.parametrize("case", ["threshold", "ties_everywhere"])
+def test_split_mask_above_one_grid_of_tiles(order, case):
+    """N = 2.5M rows: 1221 tiles of 2048 rows against a grid of 1024
+    work-groups, so the count, compact and mask kernels stride past the grid,
+    each thread of the tile scan sums two tiles, and the radix passes stride
+    over more candidates than the grid holds threads. 'threshold': every
+    Gaussian contributes, 40% pass the gradient test, 20% are selected (the
+    K-th key lies inside the scores). 'ties_everywhere': only the first 300k
+    Gaussians contribute, warm-up makes every row a candidate and K = 1.2M,
+    so the K-th key is the zero score shared by 2.2M rows in every tile,
+    taken in index order across all of them."""
+    N = 2_500_000
+    W, H = [1297, 2000, 640], [840, 1300, 480]
+    maps, off = _maps(77, W, H)
+    grad = synth.grad_accum(78, N)
+    if case == "threshold":
+        c = synth.contributions(79, N, W, H, 1, order)
+        thr, warm, budget = float(np.quantile(grad, 0.6)), False, N + N // 5
+    else:
+        c = synth.contributions(80, 300_000, W, H, 2, order)
+        thr, warm, budget = 0.0, True, N + 1_200_000
+    print(f"{case}/{order}: {c.n} contributions", flush=True)
+    K = run(N, N + 777, W, H, c, grad, thr, warm, budget, maps, off)
+    assert K == budget - N
