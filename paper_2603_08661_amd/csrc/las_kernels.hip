@@ -256,17 +256,18 @@ __device__ __forceinline__ void copy_rows4(float4* a, int w4, const int32_t* row
     if (rl.lr < 0) return;
     const int step = NWV * rl.rpw;
     for (int r0 = wv * rl.rpw + rl.lr; r0 < total; r0 += step * kWideInFlight) {
-      float4 v[kWideInFlight];
-#pragma unroll
-      for (int u = 0; u < kWideInFlight; ++u) {
-        const int r = r0 + u * step;
-        if (r < total) v[u] = a[(base + rows[r]) * w4 + rl.le];
-      }
-#pragma unroll
-      for (int u = 0; u < kWideInFlight; ++u) {
-        const int r = r0 + u * step;
-        if (r < total) a[(dst0 + r) * w4 + rl.le] = v[u];
-      }
+      // no lane branches around its loads or stores (a lane past the tile's
+      // last row copies that row again: the same bytes to the same place),
+      // so the rows stay in registers, all in flight before the stores
+      static_assert(kWideInFlight == 4, "four named rows in flight");
+      const int ra = min(r0, total - 1), rb = min(r0 + step, total - 1), rc = min(r0 + 2 * step, total - 1),
+                rd = min(r0 + 3 * step, total - 1);
+      const float4 va = a[(base + rows[ra]) * w4 + rl.le], vb = a[(base + rows[rb]) * w4 + rl.le],
+                   vc = a[(base + rows[rc]) * w4 + rl.le], vd = a[(base + rows[rd]) * w4 + rl.le];
+      a[(dst0 + ra) * w4 + rl.le] = va;
+      a[(dst0 + rb) * w4 + rl.le] = vb;
+      a[(dst0 + rc) * w4 + rl.le] = vc;
+      a[(dst0 + rd) * w4 + rl.le] = vd;
     }
   } else {
     for (int r = wv; r < total; r += NWV)
@@ -345,8 +346,12 @@ __device__ __forceinline__ void row_work(const LasLaunch& L, const int32_t* rows
 // Per live tile: the selected rows, compacted in ascending order into LDS
 // (each thread owns 8 consecutive rows; a work-group scan places them), then
 // split with every lane busy: consecutive lanes take consecutive ranks, so
-// the appended children of a wavefront are contiguous rows.
-__global__ __launch_bounds__(kLasThreads) void las_split_kernel(LasLaunch L) {
+// the appended children of a wavefront are contiguous rows. FULL adds the
+// row-wide work (feature rows, optimiser moments); the plain split (no
+// features, no moments) is compiled without it, so it keeps its registers
+// for the split itself.
+template <bool FULL>
+__device__ __forceinline__ void split_tiles(const LasLaunch& L) {
   __shared__ int32_t rows[kLasRows];
   __shared__ int wsum[kLasThreads / 64];
   if (!L.scalars->ok) return;  // uniform across the grid
@@ -366,9 +371,18 @@ __global__ __launch_bounds__(kLasThreads) void las_split_kernel(LasLaunch L) {
       const int64_t rank = first + k;
       split_row(L, base + rows[k], N + rank, rank);
     }
-    row_work(L, rows, base, N, first, total);
+    if constexpr (FULL) row_work(L, rows, base, N, first, total);
     __syncthreads();  // rows[] is rewritten by the next tile
   }
+}
+
+// The plain split fits 64 registers: eight waves per SIMD.
+__global__ __launch_bounds__(kLasThreads) __attribute__((amdgpu_waves_per_eu(8))) void las_split_kernel(LasLaunch L) {
+  split_tiles<false>(L);
+}
+
+__global__ __launch_bounds__(kLasThreads) __attribute__((amdgpu_waves_per_eu(4))) void las_split_full_kernel(LasLaunch L) {
+  split_tiles<true>(L);
 }
 
 }  // namespace
@@ -383,7 +397,12 @@ hipError_t launch_las(const LasLaunch& L, hipStream_t s) {
   hipLaunchKernelGGL(las_scan_kernel, dim3(1), dim3(1024), 0, s, L);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(las_split_kernel, dim3(grid), dim3(kLasThreads), 0, s, L);
+  const igsp_adam_moments& A = L.adam;
+  bool full = L.g.feat_dim > 0;
+  for (int m = 0; m < 2; ++m)
+    full = full || A.means[m] || A.log_scales[m] || A.quats[m] || A.opacity_logits[m] || A.features[m];
+  if (full) hipLaunchKernelGGL(las_split_full_kernel, dim3(grid), dim3(kLasThreads), 0, s, L);
+  else hipLaunchKernelGGL(las_split_kernel, dim3(grid), dim3(kLasThreads), 0, s, L);
   return hipGetLastError();
 }
 
