@@ -26,10 +26,13 @@
  *     plans (device view tables, work lists, histograms, intermediate maps,
  *     split workspaces), created on the first call with a given geometry and
  *     reused afterwards; igsp_release_plans() frees them.
- *   - A call that creates a plan may allocate device memory and is therefore
- *     not capturable into a HIP graph; repeated calls with the same geometry
- *     allocate nothing, never read device memory back to the host, and can be
- *     captured (see igsp_step_*).
+ *   - A call that creates a plan allocates device memory and synchronises
+ *     the device, so it is not capturable into a HIP graph; when more than
+ *     eight edge (or split-mask) geometries are cached, creating another one
+ *     frees the least recently used plan, which also waits for the device.
+ *     Repeated calls with a cached geometry allocate nothing, never wait,
+ *     never read device memory back to the host, and can be captured (see
+ *     igsp_step_*; a step keeps its plans alive until it is destroyed).
  *   - Errors detectable on the host return a negative status and enqueue
  *     nothing. No C++ exception crosses this boundary.
  *   - Calls on one device that share a plan must be ordered (one stream, or
@@ -55,7 +58,9 @@ typedef enum {
                                 alpha/gamma/beta outside (0, 1]                  */
   IGSP_ERR_CAPACITY = -6,    /* (device status) N + K > capacity: nothing split  */
   IGSP_ERR_HIP = -7,         /* a HIP runtime call failed (no device, OOM, ...)  */
-  IGSP_ERR_UNSUPPORTED = -8  /* the current device is not gfx950                 */
+  IGSP_ERR_UNSUPPORTED = -8, /* the current device is not gfx950                 */
+  IGSP_ERR_TIMEOUT = -9      /* (device status) a wait inside the persistent
+                                launch gave up: its maps are not valid          */
 } igsp_status;
 
 /* ------------------------------------------------------------------------ */
@@ -114,6 +119,11 @@ typedef struct {
                             last three after their final launch). Profiling
                             only: no work changes. Ignored by
                             igsp_step_create.                                  */
+  int32_t* status;       /* (device, optional) [1]: set by the call's kernels to
+                            IGSP_OK, or by the persistent form to
+                            IGSP_ERR_TIMEOUT if one of its bounded waits gave
+                            up (then the maps are not valid; the next call
+                            starts clean). Untouched when n_views = 0.        */
 } igsp_edge_opts;
 
 /*

@@ -21,11 +21,12 @@ PRECISIONS = {"fp32": FP32, "fp16": FP16, "bf16": BF16}
 STATUS = {
     0: "IGSP_OK", -1: "IGSP_ERR_NULL", -2: "IGSP_ERR_DIMS", -3: "IGSP_ERR_ALIGN",
     -4: "IGSP_ERR_OVERLAP", -5: "IGSP_ERR_PARAM", -6: "IGSP_ERR_CAPACITY",
-    -7: "IGSP_ERR_HIP", -8: "IGSP_ERR_UNSUPPORTED",
+    -7: "IGSP_ERR_HIP", -8: "IGSP_ERR_UNSUPPORTED", -9: "IGSP_ERR_TIMEOUT",
 }
 
 # Every symbol include/igsp.h declares.
-EXPORTS = ("edge_importance", "long_axis_split", "long_axis_split_full", "split_mask", "igsp_edge_autotune",
+EXPORTS = ("edge_importance", "long_axis_split", "long_axis_split_full", "split_mask",
+           "igsp_edge_autotune",
            "igsp_edge_resolve", "igsp_step_create",
            "igsp_step_launch", "igsp_step_destroy", "igsp_status_string", "igsp_release_plans", "igsp_version",
            "igsp_lr_exponential")
@@ -51,7 +52,7 @@ class EdgeOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("batched", ctypes.c_int32),
                 ("seg_rows", ctypes.c_int32), ("wg_waves", ctypes.c_int32),
                 ("medians", ctypes.c_void_p), ("survivors", ctypes.c_void_p),
-                ("stage_events", ctypes.c_void_p)]
+                ("stage_events", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
 class Gaussians(ctypes.Structure):
@@ -193,11 +194,14 @@ def form_code(batched) -> int:
 
 
 def edge_opts(precision="fp32", batched=True, seg_rows=0, wg_waves=0, medians=None, survivors=None,
-              stage_events=None):
+              stage_events=None, status=None):
     import torch
 
     _need(medians, torch.float32, "medians")
     _need(survivors, torch.int32, "survivors")
+    _need(status, torch.int32, "status")
+    if status is not None and status.numel() < 1:
+        raise ValueError("status needs one entry")
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     ev = None
     if stage_events is not None:   # 4 torch.cuda.Event, each recorded once already
@@ -208,18 +212,21 @@ def edge_opts(precision="fp32", batched=True, seg_rows=0, wg_waves=0, medians=No
         ev = ctypes.cast(arr, ctypes.c_void_p)
         _EVENT_KEEPALIVE.append(arr)
         del _EVENT_KEEPALIVE[:-8]
-    return EdgeOpts(p, form_code(batched), int(seg_rows), int(wg_waves), _ptr(medians), _ptr(survivors), ev)
+    return EdgeOpts(p, form_code(batched), int(seg_rows), int(wg_waves), _ptr(medians), _ptr(survivors), ev,
+                    _ptr(status))
 
 
 _EVENT_KEEPALIVE: list = []
 
 
 def edge_importance(images, views, out_maps, precision="fp32", batched=True, seg_rows=0, wg_waves=0,
-                    medians=None, survivors=None, stage_events=None, stream=None):
+                    medians=None, survivors=None, stage_events=None, stream=None, status=None):
     """Edge-score maps of every view into ``out_maps`` (float32, device).
 
     images: uint8 device tensor holding the packed views; views: (widths,
     heights, in_offset, out_offset) sequences or a prebuilt view table.
+    status: optional int32 device tensor, set to 0 (IGSP_OK) or, by the
+    persistent form, -9 (IGSP_ERR_TIMEOUT: the maps are not valid).
     """
     import torch
 
@@ -227,7 +234,7 @@ def edge_importance(images, views, out_maps, precision="fp32", batched=True, seg
     _need(out_maps, torch.float32, "out_maps")
     tab, n = views if isinstance(views, tuple) and isinstance(views[0], ctypes.Array) else view_table(*views)
     _check_extents(tab, n, images, out_maps, medians, survivors)
-    opts = edge_opts(precision, batched, seg_rows, wg_waves, medians, survivors, stage_events)
+    opts = edge_opts(precision, batched, seg_rows, wg_waves, medians, survivors, stage_events, status)
     _check(lib().edge_importance(_ptr(images), tab, n, _ptr(out_maps), ctypes.byref(opts), _stream(stream)),
            "edge_importance")
 
@@ -307,6 +314,12 @@ def las_params(alpha=0.5, gamma=0.85, beta=0.6):
 def long_axis_split(means, log_scales, quats, opacity_logits, count, mask, split_idx, status,
                     n_split=None, features=None, alpha=0.5, gamma=0.85, beta=0.6, stream=None):
     """Long-Axis-Split in place; N = count[0] on the device becomes N + K."""
+    _las("long_axis_split", means, log_scales, quats, opacity_logits, count, mask, split_idx, status, n_split,
+         features, alpha, gamma, beta, stream)
+
+
+def _las(entry, means, log_scales, quats, opacity_logits, count, mask, split_idx, status, n_split, features,
+         alpha, gamma, beta, stream):
     import torch
 
     _need(mask, torch.uint8, "mask")
@@ -320,8 +333,8 @@ def long_axis_split(means, log_scales, quats, opacity_logits, count, mask, split
         raise ValueError("status and n_split need one entry")
     out = LasOut(_ptr(split_idx), _ptr(status), _ptr(n_split))
     prm = las_params(alpha, gamma, beta)
-    _check(lib().long_axis_split(ctypes.byref(g), _ptr(mask), ctypes.byref(out), ctypes.byref(prm),
-                                 _stream(stream)), "long_axis_split")
+    _check(getattr(lib(), entry)(ctypes.byref(g), _ptr(mask), ctypes.byref(out), ctypes.byref(prm),
+                                 _stream(stream)), entry)
 
 
 ADAM_GROUPS = ("means", "log_scales", "quats", "opacity_logits", "features")

@@ -266,7 +266,7 @@ struct StripState {
   Lane12 rows[2];                  // raw bytes: this row / next row
   // rows r-1 (other parity slot) and r-2 (same parity slot) of:
   int h[2][4];                     // the horizontal blur
-  int tv[2][4];                    // its first vertical (1 2 1) pass
+  int e[2][4];                     // e(r) = h(r) + h(r-2)
   int sx[2][4];                    // the horizontal difference of the blur
   int hs[2][4];                    // the horizontal (1 2 1) smoothing of the blur
   float M[3][4];                   // squared magnitude of the last three rows
@@ -281,7 +281,8 @@ struct StripCtx {
   int W, H, ys, ye, T;
   bool remap;                      // some lane reorders its window (wave-uniform)
   int win_off;                     // byte offset of the lane's 4-pixel window
-  bool sel0[4], sel1[4];           // pixel i of the lane = window pixel (sel1 sel0)
+  uint32_t permA[3], permB[3];     // byte selectors that put the window's mirrored
+                                   // pixels in lane order (edge strips)
   int soff[4];                     // byte offsets of the lane's mirrored columns
   int store_off[4];                // byte offset of output pixel i in its map row, or
                                    // past the row's end (dropped) if not an output
@@ -319,14 +320,22 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   //      step keeps the wait for this row from draining the prefetch)
   S.rows[Q] = fetch_row<NARROW>(C, min(C.ys - kHalo + t + 1, C.ye + kHalo - 1));
 
-  // ---- 1. grayscale of row yy = ys - 4 + t
+  // ---- 1. grayscale of row yy = ys - 4 + t (edge strips first put the
+  //      mirrored pixels of the window in lane order: two byte permutes per
+  //      output word, the first over window bytes 0-7, the second adding
+  //      bytes 8-11)
   int g[4];
-  gray4(S.rows[P].v.x, S.rows[P].v.y, S.rows[P].v.z, g);
-  if (!NARROW && C.remap) {  // edge strips: mirrored columns into lane order
-    const int w0 = g[0], w1 = g[1], w2 = g[2], w3 = g[3];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) g[i] = C.sel1[i] ? (C.sel0[i] ? w3 : w2) : (C.sel0[i] ? w1 : w0);
+  uint32_t d0 = S.rows[P].v.x, d1 = S.rows[P].v.y, d2 = S.rows[P].v.z;
+  if (!NARROW && C.remap) {
+    asm volatile("");  // keeps this a branch that interior strips skip, not selects every strip pays for
+    const uint32_t o0 = __builtin_amdgcn_perm(d2, __builtin_amdgcn_perm(d1, d0, C.permA[0]), C.permB[0]);
+    const uint32_t o1 = __builtin_amdgcn_perm(d2, __builtin_amdgcn_perm(d1, d0, C.permA[1]), C.permB[1]);
+    const uint32_t o2 = __builtin_amdgcn_perm(d2, __builtin_amdgcn_perm(d1, d0, C.permA[2]), C.permB[2]);
+    d0 = o0;
+    d1 = o1;
+    d2 = o2;
   }
+  gray4(d0, d1, d2, g);
 
   // ---- 2. horizontal binomial taps (1 4 6 4 1)
   const int gL2 = from_left(g[2]), gL3 = from_left(g[3]);
@@ -337,14 +346,19 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
   h[2] = mad6(g[2], (g[0] + gR0) + 4 * (g[1] + g[3]));
   h[3] = mad6(g[3], (g[1] + gR1) + 4 * (g[2] + gR0));
 
-  // ---- 3. vertical taps (1 4 6 4 1) = (1 2 1) twice: b = blur of row yy-2
+  // ---- 3. vertical taps (1 4 6 4 1): b = blur of row yy-2, three
+  //      instructions per pixel from the pair sums e(r) = h(r) + h(r-2):
+  //      h(r) + 4 h(r-1) + 6 h(r-2) + 4 h(r-3) + h(r-4)
+  //        = e(r) + e(r-2) + 4 (e(r-1) + h(r-2))
+  //      (slot P holds rows r-2, slot Q rows r-1, before the update)
   int b[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int tv = S.h[P][i] + 2 * S.h[Q][i] + h[i];       // centred on row yy-1
+    const int en = h[i] + S.h[P][i];
+    const int t4 = (S.e[Q][i] + S.h[P][i]) << 2;
+    b[i] = en + S.e[P][i] + t4;
     S.h[P][i] = h[i];
-    b[i] = S.tv[P][i] + 2 * S.tv[Q][i] + tv;              // centred on row yy-2
-    S.tv[P][i] = tv;
+    S.e[P][i] = en;
   }
 
   // ---- 4. Sobel of row yy-3: gx = (1 2 1)^T on the horizontal difference,
@@ -495,13 +509,30 @@ __device__ __forceinline__ void wave_strip(const EdgeLaunch& L, const ViewDesc& 
   }
   ws = max(ws, 0);
   C.win_off = 3 * ws;
+  // Output byte q (pixel q / 3, channel q % 3) is window byte b = 3 k + q % 3
+  // for the window pixel k that holds that pixel's column. A byte permute
+  // picks bytes of {S0, S1} by selector: 0-3 = S1's bytes, 4-7 = S0's, 12 =
+  // zero. Stage A permutes (d1, d0), i.e. window bytes 0-7 at selector b;
+  // stage B permutes (d2, A) and keeps A's byte j (selector j) or takes
+  // window byte b >= 8 from d2 (selector 4 + b - 8).
   bool ident = true;
+  int kwin[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int k = min(max(sc[i] - ws, 0), 3);
-    C.sel0[i] = (k & 1) != 0;
-    C.sel1[i] = (k & 2) != 0;
-    ident = ident && k == i;
+    kwin[i] = min(max(sc[i] - ws, 0), 3);
+    ident = ident && kwin[i] == i;
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    uint32_t a = 0, b = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * m + j, src = 3 * kwin[q / 3] + q % 3;
+      a |= (uint32_t)(src < 8 ? src : 12) << (8 * j);
+      b |= (uint32_t)(src < 8 ? j : 4 + src - 8) << (8 * j);
+    }
+    C.permA[m] = a;
+    C.permB[m] = b;
   }
   const bool narrow = C.W < 4;
   C.remap = !narrow && __builtin_amdgcn_ballot_w64(!ident) != 0;
@@ -579,6 +610,7 @@ __global__ __launch_bounds__(256) void median_select_kernel(EdgeLaunch L, int v0
   static_assert(NB % 256 == 0, "bins per thread");
   __shared__ uint32_t tmp[4];
   const int v = v0 + blockIdx.x;
+  if (L.status && blockIdx.x == 0 && threadIdx.x == 0) *L.status = IGSP_OK;  // the staged stages cannot fail
   uint32_t* h = L.hist + (int64_t)v * kBinsMax;
   const int b0 = threadIdx.x * PER;
   uint32_t c[PER];
@@ -891,10 +923,10 @@ __global__ __launch_bounds__(kUfCols) void uf_nms_kernel(EdgeLaunch L, UfLaunch 
 // of the next phase wait for it. Every task waited on was handed out
 // earlier, to a work-group that is already running, so the waits end.
 
-// Bound of one wait (about half a second of polling); never reached when the
-// waited-on work is running. If it were, the launch records an error bit and
-// finishes instead of hanging.
-constexpr uint32_t kSpinLimit = 1u << 19;
+// Every wait is bounded (P.spin_limit polls, about half a second by default);
+// the bound is never reached when the waited-on work is running. If it were,
+// the launch records an error bit, finishes instead of hanging, and reports
+// IGSP_ERR_TIMEOUT through the caller's status word.
 
 __device__ __forceinline__ uint32_t ld_agent(uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -950,14 +982,17 @@ __device__ __forceinline__ uint32_t wg_excl_scan(uint32_t v, uint32_t* tmp, uint
 }
 
 // Data crosses work-groups of this launch only through device-coherent
-// accesses: the stored survivor values (kCpolAgent buffer stores and loads),
-// histograms (device-scope atomics, read back with coherent loads), the
-// selection state and the counters (relaxed agent-scope atomics). Ordering is
-// the hardware's: each wave waits for its own memory operations to complete
-// (s_waitcnt 0) before the work-group barrier that precedes the counter
-// update, and a reader issues its data loads only after the flag it waited
-// for has returned. So no release or acquire fence is needed, which on this
-// chip would write back or invalidate a whole XCD's L2 per task.
+// accesses: the stored survivor values (buffer stores and loads with the SC1
+// scope bit, kCpolAgent, which write through to and read from the
+// device-coherent level instead of an XCD's L2), histograms (device-scope
+// atomics, read back with SC1 loads), the selection state and the counters
+// (relaxed agent-scope atomics, which are SC1 accesses too). There is no
+// acquire or release fence anywhere: ordering comes from the hardware alone.
+// Each wave waits for its own memory operations to complete (s_waitcnt 0)
+// before the work-group barrier that precedes the counter update, and a
+// reader issues its data loads only after the flag load it waited for has
+// returned. A fence would instead write back or invalidate a whole XCD's L2
+// per task.
 __device__ __forceinline__ void drain() { __builtin_amdgcn_s_waitcnt(0); }
 
 // The end of one task: count it off its phase and tell every thread whether
@@ -983,13 +1018,14 @@ __device__ __forceinline__ void publish(uint32_t* ready, uint32_t level) {
   if (threadIdx.x == 0) st_agent(ready, level);
 }
 
-// Wait until a view's selection has reached `level` (all threads call it).
-__device__ __forceinline__ void await(uint32_t* ready, uint32_t level, uint32_t* error) {
+// Wait until a view's selection has reached `level` (all threads call it),
+// for at most `limit` (>= 1) polls; past that, record the error and go on.
+__device__ __forceinline__ void await(uint32_t* ready, uint32_t level, uint32_t limit, uint32_t* error) {
   if (threadIdx.x == 0) {
     uint32_t spins = 0;
     while (ld_agent(ready) < level) {
       __builtin_amdgcn_s_sleep(8);
-      if (++spins == kSpinLimit) {
+      if (++spins >= limit) {
         atomicOr(error, 1u);
         break;
       }
@@ -1032,12 +1068,22 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const EdgeLaunch& L
   return buffer_rsrc(m, n8 * (int)sizeof(T));
 }
 
+// The thread index as a value the compiler cannot prove loop-invariant, for
+// the task functions of the persistent kernel: addresses built from it are
+// then recomputed inside each task instead of being held in registers across
+// the whole task loop (where the stencil's register demand made them spill).
+__device__ __forceinline__ int task_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // First selection step of view v from its global histogram (then cleared).
 template <int PREC, int NW>
 __device__ void select_hist(const EdgeLaunch& L, int v, uint32_t* tmp) {
   constexpr int NT = NW * 64, NB = Keys<PREC>::bins, PER = (NB + NT - 1) / NT;
   uint32_t* h = L.hist + (int64_t)v * kBinsMax;
-  const int b0 = threadIdx.x * PER;
+  const int b0 = task_tid() * PER;
   uint32_t sum = 0;
   for (int k = 0; k < PER; ++k)
     if (b0 + k < NB) sum += ld_agent(h + b0 + k);
@@ -1076,7 +1122,7 @@ __device__ void select_refine(const EdgeLaunch& L, int v, int digit_bits, uint32
   uint32_t* h = L.rhist + (int64_t)v * kRefineBins;
   MedState st = load_state(L.state + v);
   const int fin = final_shift(L.precision);
-  const int b0 = threadIdx.x * PER;
+  const int b0 = task_tid() * PER;
   uint32_t sum = 0;
   for (int j = 0; j < PER; ++j)
     if (b0 + j < kRefineBins) sum += ld_agent(h + b0 + j);
@@ -1108,7 +1154,8 @@ template <int PREC, int NW>
 __device__ void refine_chunk(const EdgeLaunch& L, const FlatItem& it, const MedState& st, int digit_bits,
                              uint32_t* hs) {
   constexpr int NT = NW * 64;
-  for (int i = threadIdx.x; i < kRefineBins; i += NT) hs[i] = 0;
+  const int tid = task_tid();
+  for (int i = tid; i < kRefineBins; i += NT) hs[i] = 0;
   __syncthreads();
   if (st.n > 0 && st.shift > final_shift(PREC)) {
     const ViewDesc vd = L.views[it.view];
@@ -1116,7 +1163,7 @@ __device__ void refine_chunk(const EdgeLaunch& L, const FlatItem& it, const MedS
     const uint32_t dmask = (1u << digit_bits) - 1u;
     const __amdgpu_buffer_rsrc_t mr = chunk_rsrc<PREC>(L, vd, it);
     const int n = (int)(it.p1 - it.p0);
-    for (int p = 8 * threadIdx.x; p < n; p += 8 * NT) {
+    for (int p = 8 * tid; p < n; p += 8 * NT) {
       float v[8];
       load8_coherent<PREC>(mr, p, v);
 #pragma unroll
@@ -1128,7 +1175,7 @@ __device__ void refine_chunk(const EdgeLaunch& L, const FlatItem& it, const MedS
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kRefineBins; i += NT) {
+  for (int i = tid; i < kRefineBins; i += NT) {
     const uint32_t c = hs[i];
     if (c) atomicAdd(&L.rhist[(int64_t)it.view * kRefineBins + i], c);
   }
@@ -1144,7 +1191,7 @@ __device__ void norm_chunk(const EdgeLaunch& L, const FlatItem& it, float med) {
   gptr<float> out = as_global(L.out + vd.out_off + it.p0);
   const bool aligned = ((vd.out_off + it.p0) & 3) == 0;
   const int n = (int)(it.p1 - it.p0);
-  for (int p0 = 8 * threadIdx.x; p0 < n; p0 += kNormUnroll * STEP) {
+  for (int p0 = 8 * task_tid(); p0 < n; p0 += kNormUnroll * STEP) {
     float v[kNormUnroll][8];
 #pragma unroll
     for (int u = 0; u < kNormUnroll; ++u) load8_coherent<PREC>(mr, p0 + u * STEP, v[u]);  // past the end: 0
@@ -1191,7 +1238,8 @@ edge_persistent_kernel(EdgeLaunch L, PersistLaunch P) {
     if (tk.type == kTaskStencil) {
       const EdgeItem it = L.items[tk.idx];
       const ViewDesc vd = L.views[v];
-      for (int i = threadIdx.x; i < NB; i += NT) lds[i] = 0;
+      const int tid = task_tid();
+      for (int i = tid; i < NB; i += NT) lds[i] = 0;
       __syncthreads();
       const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
       const int ys = it.y0 + w * L.seg_rows;
@@ -1199,7 +1247,7 @@ edge_persistent_kernel(EdgeLaunch L, PersistLaunch P) {
       if (ys < ye) wave_strip<PREC, kCpolAgent>(L, vd, it.x0, ys, ye, lds);
       __syncthreads();
       uint32_t* gh = L.hist + (int64_t)v * kBinsMax;
-      for (int i = threadIdx.x; i < NB; i += NT) {
+      for (int i = tid; i < NB; i += NT) {
         const uint32_t c = lds[i];
         if (c) atomicAdd(gh + i, c);
       }
@@ -1210,7 +1258,7 @@ edge_persistent_kernel(EdgeLaunch L, PersistLaunch P) {
     } else {
       const uint32_t need = (uint32_t)tk.phase;
       if (acq_view != v || acq_level < need) {
-        await(&sy->ready, need, &P.ctl->error);
+        await(&sy->ready, need + P.wait_bias, P.spin_limit, &P.ctl->error);
         acq_view = v;
         acq_level = need;
       }
@@ -1230,9 +1278,25 @@ edge_persistent_kernel(EdgeLaunch L, PersistLaunch P) {
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && atomicAdd(&P.ctl->exited, 1u) == gridDim.x - 1) {
-    st_agent(&P.ctl->queue, 0u);
-    st_agent(&P.ctl->exited, 0u);
+  // The last work-group to leave reports the launch's status and restores
+  // the queue. After a timeout a view's readiness level may be left behind
+  // (a phase that went on without its predecessor), so every level is reset:
+  // the next launch starts clean. (The phase counters are restored by their
+  // last task in any case, and the histograms by the selection steps.)
+  if (threadIdx.x == 0) s_flag = atomicAdd(&P.ctl->exited, 1u) == gridDim.x - 1 ? 1u : 0u;
+  __syncthreads();
+  if (s_flag) {
+    const uint32_t err = ld_agent(&P.ctl->error);
+    if (err)
+      for (int v = threadIdx.x; v < P.n_views; v += NT) st_agent(&P.sync[v].ready, 0u);
+    drain();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (L.status) *L.status = err ? IGSP_ERR_TIMEOUT : IGSP_OK;
+      st_agent(&P.ctl->error, 0u);
+      st_agent(&P.ctl->queue, 0u);
+      st_agent(&P.ctl->exited, 0u);
+    }
   }
 }
 

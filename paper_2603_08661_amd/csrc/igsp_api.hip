@@ -34,11 +34,13 @@ struct DeviceInfo {
   bool checked = false;
   bool ok = false;
 };
-std::map<int, DeviceInfo> g_dev;
+constexpr int kMaxDevices = 64;
+DeviceInfo g_dev[kMaxDevices];  // a fixed table: checking a device allocates nothing
 
 igsp_status check_device(int* dev_out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return IGSP_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return IGSP_ERR_UNSUPPORTED;
   DeviceInfo& d = g_dev[dev];
   if (!d.checked) {
     hipDeviceProp_t prop;
@@ -424,6 +426,7 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
   L.medians_dn = opts ? opts->medians : nullptr;
   L.survivors = opts ? opts->survivors : nullptr;
   L.stage_events = opts ? reinterpret_cast<hipEvent_t*>(opts->stage_events) : nullptr;
+  L.status = opts ? opts->status : nullptr;
   L.precision = P->key.precision;
   L.wg_waves = P->key.wg_waves;
   L.seg_rows = P->key.seg_rows;
@@ -466,6 +469,17 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
     PL.ctl = P->d_ctl;
     PL.n_tasks = P->n_tasks;
     PL.levels = (int)passes.size();
+    PL.n_views = P->n_views;
+    PL.spin_limit = kSpinLimit;
+    PL.wait_bias = 0;
+    // Test facility: IGSP_PERSIST_FORCE_TIMEOUT=1 makes every wait of the
+    // persistent form give up after a few polls (the level it waits for is
+    // never reached), so the timeout path runs and every kernel still exits.
+    const char* force = std::getenv("IGSP_PERSIST_FORCE_TIMEOUT");
+    if (force && force[0] == '1') {
+      PL.spin_limit = 16;
+      PL.wait_bias = 1u << 24;
+    }
     EdgeLaunch LP = L;
     LP.flat = P->d_pflat;
     e = launch_edge_persistent(LP, PL, P->grid, s);
@@ -530,8 +544,10 @@ igsp_status get_las_plan(int64_t capacity, std::shared_ptr<LasPlan>* out) {
   return IGSP_OK;
 }
 
-igsp_status enqueue_las(LasPlan* P, const igsp_gaussians* g, const igsp_adam_moments* adam, const uint8_t* mask,
-                        const igsp_las_out* out, const igsp_las_params* p, hipStream_t s) {
+// The launch description of a split; its workspace fields are left for the
+// caller (a plan, or the fixed array of the allocation-free entry point).
+LasLaunch las_launch(const igsp_gaussians* g, const igsp_adam_moments* adam, const uint8_t* mask,
+                     const igsp_las_out* out, const igsp_las_params* p) {
   const double a = p ? p->alpha : 0.5, gm = p ? p->gamma : 0.85, b = p ? p->beta : 0.6;
   LasLaunch L;
   L.g = *g;
@@ -546,6 +562,16 @@ igsp_status enqueue_las(LasPlan* P, const igsp_gaussians* g, const igsp_adam_mom
   L.ln_gamma = (float)std::log(gm);
   L.ln_beta = (float)std::log(b);
   L.one_minus_beta = (float)(1.0 - b);
+  L.block_counts = nullptr;
+  L.block_offsets = nullptr;
+  L.scalars = nullptr;
+  L.n_blocks = (int)std::max<int64_t>(1, (g->capacity + kLasRows - 1) / kLasRows);
+  return L;
+}
+
+igsp_status enqueue_las(LasPlan* P, const igsp_gaussians* g, const igsp_adam_moments* adam, const uint8_t* mask,
+                        const igsp_las_out* out, const igsp_las_params* p, hipStream_t s) {
+  LasLaunch L = las_launch(g, adam, mask, out, p);
   L.block_counts = P->d_counts;
   L.block_offsets = P->d_offsets;
   L.scalars = P->d_scalars;
@@ -717,13 +743,13 @@ extern "C" igsp_status igsp_edge_resolve(const igsp_view* views, int32_t n_views
 extern "C" igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view* views, int32_t n_views,
                                           float* out_maps, int32_t precision, int32_t batched,
                                           igsp_edge_opts* best, void* stream) {
-  igsp_edge_opts base{precision, batched, 0, 0, nullptr, nullptr, nullptr};
+  igsp_edge_opts base{precision, batched, 0, 0, nullptr, nullptr, nullptr, nullptr};
   EdgeExtent ext{};
   igsp_status st = validate_edge(images, views, n_views, out_maps, &base, &ext);
   if (st != IGSP_OK) return st;
   if (n_views == 0) return IGSP_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  static const int kSeg[] = {32, 48, 64, 96, 128};
+  static const int kSeg[] = {32, 48, 64, 96, 128, 192, 256};
   static const int kWaves[] = {1, 2, 4, 8};
   std::vector<int> forms;
   if (batched == IGSP_BATCHED) forms = {IGSP_BATCHED_STAGED, IGSP_BATCHED_PERSISTENT};
@@ -810,7 +836,7 @@ extern "C" igsp_status igsp_step_create(const uint8_t* images, const igsp_view* 
     if (hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess) return IGSP_ERR_HIP;
     cs = own;
   }
-  igsp_edge_opts eo = opts ? *opts : igsp_edge_opts{IGSP_FP32, 1, 0, 0, nullptr, nullptr, nullptr};
+  igsp_edge_opts eo = opts ? *opts : igsp_edge_opts{IGSP_FP32, 1, 0, 0, nullptr, nullptr, nullptr, nullptr};
   eo.stage_events = nullptr;  // no event records inside a graph
   opts = &eo;
   auto s = std::make_unique<igsp_step>();

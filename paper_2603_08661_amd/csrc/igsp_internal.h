@@ -82,6 +82,7 @@ struct EdgeLaunch {
   float* medians_dn;         // optional outputs
   int32_t* survivors;
   hipEvent_t* stage_events;  // optional, 4 events
+  int32_t* status;           // optional device status word
   int precision;
   int wg_waves;
   int seg_rows;
@@ -121,8 +122,16 @@ struct PersistLaunch {
   PViewSync* sync;
   PCtl* ctl;
   int32_t n_tasks;
-  int32_t levels;    // refinement passes: BF16 0, FP16 1, FP32 2
+  int32_t levels;      // refinement passes: BF16 0, FP16 1, FP32 2
+  int32_t n_views;
+  uint32_t spin_limit; // polls before a wait gives up (>= 1)
+  uint32_t wait_bias;  // added to every awaited level: 0, or (host-forced
+                       // timeouts, for tests) a level no view ever reaches
 };
+
+// Polls of one wait of the persistent form before it gives up (about half a
+// second); the host can shorten it to force the timeout path in tests.
+constexpr uint32_t kSpinLimit = 1u << 19;
 
 // The unfused form (the paper's layout, kept as an ablation): one kernel per
 // step over tiles of 256 columns x kUfRows rows, each step's result in HBM.

@@ -101,6 +101,7 @@ extern "C" const char* igsp_status_string(int32_t status) {
     case IGSP_ERR_CAPACITY: return "capacity exceeded: nothing was split";
     case IGSP_ERR_HIP: return "HIP runtime error";
     case IGSP_ERR_UNSUPPORTED: return "unsupported device (gfx950 required)";
+    case IGSP_ERR_TIMEOUT: return "a wait inside the persistent launch gave up: its maps are not valid";
     default: return "unknown status";
   }
 }

@@ -122,7 +122,7 @@ def test_product_path_never_touches_the_oracle():
 
 def test_view_struct_layout_matches_header():
     assert ctypes.sizeof(B.View) == 24
-    assert ctypes.sizeof(B.EdgeOpts) == 40
+    assert ctypes.sizeof(B.EdgeOpts) == 48
     assert ctypes.sizeof(B.Gaussians) == 64
     assert ctypes.sizeof(B.LasOut) == 24
     assert np.dtype([("w", "<i4"), ("h", "<i4"), ("i", "<i8"), ("o", "<i8")]).itemsize == 24

@@ -144,3 +144,60 @@ def test_full_size_workloads_sampled(name, precisions, sample):
         assert (nsv > 0).all() and (med > 0).all()
         E2, med2, nsv2 = gpu_edge(vb, p, "staged")
         assert (E2 == E).all() and (med2 == med).all() and (nsv2 == nsv).all()
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_status_word_and_forced_persistent_timeout(precision, monkeypatch):
+    """Every form sets the caller's status word to IGSP_OK. The persistent
+    form reports IGSP_ERR_TIMEOUT when its bounded waits give up: the host
+    forces that here (IGSP_PERSIST_FORCE_TIMEOUT makes every wait give up
+    after a few polls, so every kernel still exits), and the next call, with
+    the normal bound, starts clean and matches the oracle again."""
+    import torch
+
+    import paper_2603_08661_amd as igsp
+
+    vb = small_batch(in_align=16, out_align=4)
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(np.concatenate([vb.rgb, np.zeros(32, np.uint8)])).to(dev)
+    out = torch.zeros(vb.out_floats, dtype=torch.float32, device=dev)
+    status = torch.full((1,), 99, dtype=torch.int32, device=dev)
+    views = (vb.widths, vb.heights, vb.in_offset, vb.out_offset)
+    refs = [oracle.edge_view(vb.view(v)) for v in range(vb.n)]
+
+    def run(form):
+        status.fill_(99)
+        igsp.edge_importance(img, views, out, precision=precision, batched=form, status=status)
+        torch.cuda.synchronize()
+        return int(status.item())
+
+    def check():
+        E = out.cpu().numpy()
+        for v in range(vb.n):
+            compare_view(view_map(E, vb, v), refs[v], precision)
+
+    for form in ("plain", "staged", "persistent", "unfused"):
+        assert run(form) == 0, form
+        check()
+    monkeypatch.setenv("IGSP_PERSIST_FORCE_TIMEOUT", "1")
+    print("forcing the persistent form's waits to give up", flush=True)
+    assert run("persistent") == -9
+    monkeypatch.delenv("IGSP_PERSIST_FORCE_TIMEOUT")
+    for _ in range(2):
+        assert run("persistent") == 0
+        check()
+
+
+def test_more_geometries_than_the_plan_cache_holds():
+    """Ten geometries, each called twice in interleaved order: the library
+    keeps eight edge plans and frees the least recently used one when it
+    builds another, so the second round rebuilds plans it evicted. Every map
+    matches the oracle."""
+    sizes = [(40 + 23 * k, 30 + 11 * k) for k in range(10)]
+    batches = [synth.pack_views([synth.image(900 + k, w, h, n_poly=5, texture=True)], in_align=16, out_align=4)
+               for k, (w, h) in enumerate(sizes)]
+    refs = [oracle.edge_view(vb.view(0)) for vb in batches]
+    for rnd in range(2):
+        for k in (list(range(10)) if rnd == 0 else list(range(9, -1, -2)) + list(range(0, 10, 2))):
+            E, med, nsv = gpu_edge(batches[k], "bf16", "staged")
+            compare_view(view_map(E, batches[k], 0), refs[k], "bf16", med[0], nsv[0])
