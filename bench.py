@@ -37,7 +37,7 @@ VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes per cycle x cl
 # halo rows and columns every strip recomputes, its set-up or the histogram
 # flush. Counted from the kernel's gfx950 code; a CPU test recompiles the
 # kernel and checks these figures against it.
-LOOP_LANE_OPS_PER_PX = {"fp32": 42.75, "fp16": 46.75, "bf16": 43.25}
+LOOP_LANE_OPS_PER_PX = {"fp32": 41.75, "fp16": 45.75, "bf16": 42.25}
 COPY_CAL_BYTES = 1 << 30
 STORE_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
 
@@ -310,6 +310,9 @@ def main():
                     help="skip the unfused (one launch per step) form of the same batch")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     ap.add_argument("--stage-reps", type=int, default=10)
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the compact lines of the four other workloads (single views, the 200- and "
+                         "150-view batches)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner on this batch first (default: the library's tuned table)")
     ap.add_argument("--form", default="batched", choices=["batched", "staged", "persistent"],
@@ -548,6 +551,77 @@ def main():
             plain["gaussians_split_per_s"] = round(K / (pms * 1e-3), 1)
         log(f"plain fp32: {pms:.3f} ms/step")
 
+    # ---- the other workloads, compact: each in its primary form beside the
+    #      plain per-view FP32 form of the same views (and, for the two
+    #      single views, their split); the 150-view batch in FP16 and BF16
+    others = None
+    acc_sample = []      # (workload, precision, view index, that view's map) for the accuracy check
+    if not args.no_other_workloads:
+        others = {}
+        for name in ("view_256x192", "view_1297x840", "views200_w1000_1560", "views150_2473x1643_mixed"):
+            ow = synth.workload(name)
+            t1 = time.time()
+            ovb = ow.render()
+            oimg = torch.from_numpy(np.concatenate([ovb.rgb, np.zeros(16, np.uint8)])).to(dev)
+            oout = torch.zeros(ovb.out_floats, dtype=torch.float32, device=dev)
+            oviews = (ovb.widths, ovb.heights, ovb.in_offset, ovb.out_offset)
+            ompx = ovb.pixels / 1e6
+            single = ovb.n == 1
+            reps = 200 if single else 10
+            entry = {"workload": ow.name, "views": int(ovb.n), "megapixels": round(ompx, 3)}
+            for p in ow.extra.get("precisions", [ow.precision]):
+                form = "plain" if single else "batched"
+                oform, oseg, owgw = igsp.edge_resolve(oviews, p, form, 0, 0)
+
+                def run_edge(p=p, oform=oform):
+                    igsp.edge_importance(oimg, oviews, oout, precision=p, batched=oform, stream=stream)
+                ems, _ = timed(run_edge, 3, reps)
+                r = {"form": f"{'plain per-view' if single else 'batched (' + oform + ')'} {p}",
+                     "tile": f"{oseg}x{owgw}", "edge_ms": round(ems, 4), "mpx_per_s": round(ompx / (ems * 1e-3), 1)}
+                if not single:
+                    r["algorithmic_GBps"] = round(ovb.pixels * 7 / (ems * 1e-3) / 1e9, 1)
+                    r["frac_of_hbm_peak"] = round(ovb.pixels * 7 / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                entry[p] = r
+                if name == "views150_2473x1643_mixed":
+                    E = oout.cpu().numpy()
+                    for v in (0, 1):
+                        o, W_, H_ = int(ovb.out_offset[v]), int(ovb.widths[v]), int(ovb.heights[v])
+                        acc_sample.append((name, p, v, ovb.view(v), E[o:o + W_ * H_].reshape(H_, W_).copy()))
+            if not single:
+                def run_plain32():
+                    igsp.edge_importance(oimg, oviews, oout, precision="fp32", batched=False, stream=stream)
+                pms, _ = timed(run_plain32, 1, 3)
+                best = min(entry[p]["edge_ms"] for p in ow.extra.get("precisions", [ow.precision]))
+                entry["plain_fp32"] = {"edge_ms": round(pms, 4), "mpx_per_s": round(ompx / (pms * 1e-3), 1)}
+                entry["speedup_vs_plain_fp32"] = round(pms / best, 3)
+            if ow.n_gauss > 0:
+                og = ow.gaussian_set()
+                omk = ow.split_mask()
+                oN, oK = ow.n_gauss, ow.n_split
+                ocap = oN + oK * (reps + 4)
+                OG = {}
+                for k in ("means", "log_scales", "quats", "opacity_logits"):
+                    a = getattr(og, k)
+                    OG[k] = torch.zeros((ocap,) + a.shape[1:], dtype=torch.float32, device=dev)
+                    OG[k][:oN] = torch.from_numpy(a).to(dev)
+                ocnt = torch.tensor([oN], dtype=torch.int64, device=dev)
+                omask = torch.zeros(ocap, dtype=torch.uint8, device=dev)
+                omask[:oN] = torch.from_numpy(omk).to(dev)
+                osidx = torch.zeros(ocap, dtype=torch.int32, device=dev)
+                ost = torch.zeros(1, dtype=torch.int32, device=dev)
+
+                def run_split():
+                    igsp.long_axis_split(OG["means"], OG["log_scales"], OG["quats"], OG["opacity_logits"], ocnt,
+                                         omask, osidx, ost, stream=stream)
+                lms, _ = timed(run_split, 1, reps)
+                assert int(ost.item()) == 0, "split reported a capacity error"
+                entry["las"] = {"gaussians": oN, "split": oK, "ms": round(lms, 4),
+                                "gaussians_split_per_s": round(oK / (lms * 1e-3), 1)}
+                del OG, omask, osidx
+            del oimg, oout
+            others[name] = entry
+            log(f"workload {name}: {entry} ({time.time() - t1:.1f}s)")
+
     # ---- CPU oracle on a bounded sample
     cpu = None
     if not args.no_cpu_baseline:
@@ -593,6 +667,31 @@ def main():
             cpu["gaussians_split_per_s"] = round(r["K"] / tl, 1) if r["status"] == 0 else None
             cpu["sample"] += f"; split of the first {n_l} Gaussians ({r['K']} selected) on 1 thread, {tl:.2f}s"
         log(f"cpu baseline: {cpu}")
+        # The oracle's maps of the sampled views of the 150-view batch, against
+        # the maps this run's GPU form wrote for them: suppression decisions
+        # that differ (and how many of those the oracle's margin exempts), the
+        # map error over equal decisions, scaled by max(1, E) and plain.
+        refs = {}
+        for name, p, v, rgb, Eg in acc_sample:
+            if (name, v) not in refs:
+                refs[(name, v)] = oracle.edge_view(rgb)
+            ref = refs[(name, v)]
+            keep_g, keep_r = Eg > 0, ref["keep"] > 0
+            mism = keep_g != keep_r
+            same = ~mism
+            d = np.abs(Eg.astype(np.float64) - ref["E"])[same]
+            a = others[name][p].setdefault("accuracy", {"views": [], "pixels": 0, "decisions_differing": 0,
+                                                        "differing_not_exempt": 0, "max_scaled_err": 0.0,
+                                                        "max_abs_err": 0.0})
+            a["views"].append(v)
+            a["pixels"] += int(Eg.size)
+            a["decisions_differing"] += int(mism.sum())
+            a["differing_not_exempt"] += int((mism & (ref["margin"] >= 1e-6)).sum())
+            a["max_scaled_err"] = max(a["max_scaled_err"], float((d / np.maximum(1.0, ref["E"][same])).max()))
+            a["max_abs_err"] = max(a["max_abs_err"], float(d.max()))
+        for name, p, *_ in acc_sample:
+            a = others[name][p]["accuracy"]
+            a["mismatch_rate"] = a["decisions_differing"] / max(a["pixels"], 1)
 
     prof = profile_facts(kernel, prec, w.name, seg, wgw)
     traffic = prof.get("traffic_bytes_per_launch")
@@ -672,6 +771,8 @@ def main():
         res["las_full_record"] = las_full
     if unfused:
         res["unfused"] = unfused
+    if others:
+        res["other_workloads"] = others
     if plain:
         res["plain_fp32"] = plain
         res["speedup_vs_plain_fp32"] = round(plain["ms_per_step"] / ms, 3)
