@@ -59,8 +59,10 @@ typedef enum {
   IGSP_ERR_CAPACITY = -6,    /* (device status) N + K > capacity: nothing split  */
   IGSP_ERR_HIP = -7,         /* a HIP runtime call failed (no device, OOM, ...)  */
   IGSP_ERR_UNSUPPORTED = -8, /* the current device is not gfx950                 */
-  IGSP_ERR_TIMEOUT = -9      /* (device status) a wait inside the persistent
+  IGSP_ERR_TIMEOUT = -9,     /* (device status) a wait inside the persistent
                                 launch gave up: its maps are not valid          */
+  IGSP_ERR_TOO_LARGE = -10   /* capacity beyond the fixed workspace of
+                                long_axis_split_noalloc                         */
 } igsp_status;
 
 /* ------------------------------------------------------------------------ */
@@ -234,6 +236,22 @@ typedef struct {
  */
 igsp_status long_axis_split(const igsp_gaussians* g, const uint8_t* mask, const igsp_las_out* out,
                             const igsp_las_params* params, void* stream);
+
+/*
+ * long_axis_split for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and result as long_axis_split (features included),
+ * but its workspace (per-tile counts and offsets, the split's scalars) is a
+ * fixed device array of the library, about 1.5 MiB per GPU, held from the
+ * first call on a device until the process ends. Calls no hipMalloc or
+ * hipFree, never synchronises, and builds no plan.
+ * Limit: capacity <= 2^28 rows, else IGSP_ERR_TOO_LARGE and nothing enqueued.
+ * Every call on one GPU shares that GPU's workspace: calls that overlap on a
+ * GPU (different streams without ordering, several host threads) race and
+ * must be serialised by the caller; consecutive calls on one stream are safe.
+ */
+igsp_status long_axis_split_noalloc(const igsp_gaussians* g, const uint8_t* mask, const igsp_las_out* out,
+                                    const igsp_las_params* params, void* stream);
 
 /*
  * Adam moments kept by the caller's optimiser for each parameter group, in

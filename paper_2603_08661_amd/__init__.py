@@ -11,6 +11,8 @@ Hand-written HIP behind the C ABI of include/igsp.h (arXiv 2603.08661):
 * ``long_axis_split`` -- Long-Axis-Split of selected Gaussians (Sec. 2.2,
   Algorithms 1 and 2), in place into pre-allocated capacity;
   ``long_axis_split_full`` adds feature rows and the optimiser's moments;
+  ``long_axis_split_noalloc`` is the split for callers that cannot allocate
+  (a fixed workspace of the library, capacity up to 2^28 rows);
 * ``split_mask`` -- which Gaussians to split: edge scores moved onto the
   Gaussians through pixel contributions, the gradient threshold with its
   warm-up, and a budget;
@@ -22,5 +24,6 @@ HIP graph.
 from ._binding import (  # noqa: F401
     BATCHED, BATCHED_PERSISTENT, BATCHED_STAGED, BF16, EXPORTS, FORMS, FP16, FP32, LIB_PATH, PLAIN, PRECISIONS,
     IgspError, Step, edge_autotune, edge_importance, edge_resolve, form_code, lib, long_axis_split, long_axis_split_full,
+    long_axis_split_noalloc,
     lr_exponential, release_plans, split_mask, status_string, view_table,
 )

@@ -21,11 +21,11 @@ PRECISIONS = {"fp32": FP32, "fp16": FP16, "bf16": BF16}
 STATUS = {
     0: "IGSP_OK", -1: "IGSP_ERR_NULL", -2: "IGSP_ERR_DIMS", -3: "IGSP_ERR_ALIGN",
     -4: "IGSP_ERR_OVERLAP", -5: "IGSP_ERR_PARAM", -6: "IGSP_ERR_CAPACITY",
-    -7: "IGSP_ERR_HIP", -8: "IGSP_ERR_UNSUPPORTED", -9: "IGSP_ERR_TIMEOUT",
+    -7: "IGSP_ERR_HIP", -8: "IGSP_ERR_UNSUPPORTED", -9: "IGSP_ERR_TIMEOUT", -10: "IGSP_ERR_TOO_LARGE",
 }
 
 # Every symbol include/igsp.h declares.
-EXPORTS = ("edge_importance", "long_axis_split", "long_axis_split_full", "split_mask",
+EXPORTS = ("edge_importance", "long_axis_split", "long_axis_split_noalloc", "long_axis_split_full", "split_mask",
            "igsp_edge_autotune",
            "igsp_edge_resolve", "igsp_step_create",
            "igsp_step_launch", "igsp_step_destroy", "igsp_status_string", "igsp_release_plans", "igsp_version",
@@ -104,6 +104,8 @@ def lib():
         L.long_axis_split.argtypes = [ctypes.POINTER(Gaussians), vp, ctypes.POINTER(LasOut),
                                       ctypes.POINTER(LasParams), vp]
         L.long_axis_split.restype = i32
+        L.long_axis_split_noalloc.argtypes = L.long_axis_split.argtypes
+        L.long_axis_split_noalloc.restype = i32
         L.long_axis_split_full.argtypes = [ctypes.POINTER(Gaussians), ctypes.POINTER(AdamMoments), vp,
                                            ctypes.POINTER(LasOut), ctypes.POINTER(LasParams), vp]
         L.long_axis_split_full.restype = i32
@@ -316,6 +318,14 @@ def long_axis_split(means, log_scales, quats, opacity_logits, count, mask, split
     """Long-Axis-Split in place; N = count[0] on the device becomes N + K."""
     _las("long_axis_split", means, log_scales, quats, opacity_logits, count, mask, split_idx, status, n_split,
          features, alpha, gamma, beta, stream)
+
+
+def long_axis_split_noalloc(means, log_scales, quats, opacity_logits, count, mask, split_idx, status,
+                            n_split=None, features=None, alpha=0.5, gamma=0.85, beta=0.6, stream=None):
+    """long_axis_split with the library's fixed workspace: allocates nothing
+    (capacity up to 2^28 rows). Calls that overlap on one GPU race."""
+    _las("long_axis_split_noalloc", means, log_scales, quats, opacity_logits, count, mask, split_idx, status,
+         n_split, features, alpha, gamma, beta, stream)
 
 
 def _las(entry, means, log_scales, quats, opacity_logits, count, mask, split_idx, status, n_split, features,

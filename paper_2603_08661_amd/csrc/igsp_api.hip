@@ -579,6 +579,55 @@ igsp_status enqueue_las(LasPlan* P, const igsp_gaussians* g, const igsp_adam_mom
   return launch_las(L, s) == hipSuccess ? IGSP_OK : IGSP_ERR_HIP;
 }
 
+}  // namespace
+
+// ------------------------------------------------------------------ allocation-free LAS
+//
+// Workspace of long_axis_split_noalloc: the per-tile selected counts, their
+// exclusive offsets and the split's scalars, in a fixed device array (one
+// copy per GPU, held until the process ends). Nothing in it needs to start at
+// zero: the count kernel writes every live tile's count, the scan kernel every
+// live tile's offset and all the scalars, before anything reads them.
+constexpr int64_t kNoAllocCapacity = int64_t(1) << 28;   // rows
+constexpr int kNoAllocTiles = (int)(kNoAllocCapacity / kLasRows);
+struct LasScratch {
+  LasScalars scalars;
+  int64_t offsets[kNoAllocTiles];
+  int32_t counts[kNoAllocTiles];
+};
+static_assert(kNoAllocCapacity % kLasRows == 0, "whole tiles");
+static_assert(sizeof(LasScratch) < (size_t(2) << 20), "under 2 MiB per GPU");
+
+// In host code this name stands for the array but is not its device
+// address: only the pointer hipGetSymbolAddress returns for the current
+// device may reach a kernel or a copy.
+static __device__ __align__(256) LasScratch scratch;
+
+namespace {
+
+struct ScratchSlot {
+  bool resolved = false;
+  char* ptr = nullptr;
+};
+ScratchSlot g_scratch[kMaxDevices];
+
+// The device address of this device's `scratch`, looked up once per device
+// with that device current (caller holds g_mu).
+igsp_status scratch_of_device(char** out) {
+  int dev = 0;
+  igsp_status st = check_device(&dev);
+  if (st != IGSP_OK) return st;
+  ScratchSlot& s = g_scratch[dev];
+  if (!s.resolved) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return IGSP_ERR_HIP;
+    s.ptr = static_cast<char*>(p);
+    s.resolved = true;
+  }
+  *out = s.ptr;
+  return IGSP_OK;
+}
+
 // ------------------------------------------------------------------ split mask
 
 struct SelPlan {
@@ -704,6 +753,25 @@ extern "C" igsp_status long_axis_split(const igsp_gaussians* g, const uint8_t* m
   st = get_las_plan(g->capacity, &plan);
   if (st != IGSP_OK) return st;
   return enqueue_las(plan.get(), g, nullptr, mask, out, params, static_cast<hipStream_t>(stream));
+}
+
+extern "C" igsp_status long_axis_split_noalloc(const igsp_gaussians* g, const uint8_t* mask,
+                                               const igsp_las_out* out, const igsp_las_params* params,
+                                               void* stream) {
+  igsp_status st = validate_las(g, mask, out, params);
+  if (st != IGSP_OK) return st;
+  if (g->capacity > kNoAllocCapacity) return IGSP_ERR_TOO_LARGE;
+  char* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    st = scratch_of_device(&ws);
+  }
+  if (st != IGSP_OK) return st;
+  LasLaunch L = las_launch(g, nullptr, mask, out, params);
+  L.scalars = reinterpret_cast<LasScalars*>(ws + offsetof(LasScratch, scalars));
+  L.block_offsets = reinterpret_cast<int64_t*>(ws + offsetof(LasScratch, offsets));
+  L.block_counts = reinterpret_cast<int32_t*>(ws + offsetof(LasScratch, counts));
+  return launch_las(L, static_cast<hipStream_t>(stream)) == hipSuccess ? IGSP_OK : IGSP_ERR_HIP;
 }
 
 extern "C" igsp_status long_axis_split_full(const igsp_gaussians* g, const igsp_adam_moments* adam,

@@ -102,6 +102,7 @@ extern "C" const char* igsp_status_string(int32_t status) {
     case IGSP_ERR_HIP: return "HIP runtime error";
     case IGSP_ERR_UNSUPPORTED: return "unsupported device (gfx950 required)";
     case IGSP_ERR_TIMEOUT: return "a wait inside the persistent launch gave up: its maps are not valid";
+    case IGSP_ERR_TOO_LARGE: return "capacity above the fixed workspace of the allocation-free split (2^28 rows)";
     default: return "unknown status";
   }
 }

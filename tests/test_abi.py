@@ -104,6 +104,25 @@ def test_las_validation():
         assert las(prm=B.LasParams(a, gm, b)) == -5
 
 
+def test_las_noalloc_validation():
+    """The allocation-free split validates like long_axis_split and rejects a
+    capacity above its fixed workspace before touching the GPU."""
+    L = igsp.lib()
+    out = B.LasOut(0x60, 0x70, None)
+
+    def call(g, mask=0x1000):
+        return L.long_axis_split_noalloc(ctypes.byref(g), mask, ctypes.byref(out), None, None)
+
+    assert L.long_axis_split_noalloc(None, 0x1000, None, None, None) == -1
+    assert call(B.Gaussians(0x10, 0x20, 0x30, 0x40, None, 0, 0x50, 100), mask=0) == -1
+    assert call(B.Gaussians(0x10, 0, 0x30, 0x40, None, 0, 0x50, 100)) == -1
+    assert call(B.Gaussians(0x10, 0x20, 0x30, 0x40, None, 0, 0x50, -1)) == -2
+    assert call(B.Gaussians(0x10, 0x20, 0x30, 0x40, None, -1, 0x50, 100)) == -5
+    assert call(B.Gaussians(0x10, 0x20, 0x30, 0x40, None, 0, 0x50, 2 ** 28 + 1)) == -10
+    assert call(B.Gaussians(0x10, 0x20, 0x30, 0x40, None, 0, 0x50, 2 ** 31 - 1)) == -10
+    assert "workspace" in igsp.status_string(-10)
+
+
 def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/libigsp.so")
     monkeypatch.setattr(B, "_lib", None)
