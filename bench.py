@@ -110,13 +110,15 @@ def summarise_profile(d: str, copy_bytes: int):
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     wl = res["config"]["workload"]
     tag = f"{kernel}_w{res['config']['views']}v_{res['config']['intermediate']}"
-    bench_cmd = "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline"
+    bench_cmd = "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-other-workloads"
     lines = [f"# Kernel trace: {wl}", "",
              "Command (repo root, TMPDIR=/tmp):", "",
              f"    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/trace -o t -- {bench_cmd}"
              " > <dir>/bench.json", "",
              f"Benchmark line of that run: form `{res['config']['form']}`, tile {res['config']['tile']}, "
              f"{res['ms_per_step']} ms/step; live HIP-event time of `{kernel}`: {res['stage_ms']['fused']} ms.", "",
+             "The four other workloads are left out of profiled runs (`--no-other-workloads`): they run the same "
+             "kernels at other sizes, and would mix into the averages below.", "",
              "Every kernel of the run (the bench times the graph-captured step, then each further form and row "
              "on its own: the plain per-view FP32 form is the many small launches), with the part of the hot "
              "path it belongs to:", "",
@@ -151,7 +153,7 @@ def summarise_profile(d: str, copy_bytes: int):
     f_write = copy_bytes / (cw * 1024) if cw else None
     traffic = (fetch * 1024 * f_fetch + write * 1024 * f_write) if None not in (fetch, write, f_fetch, f_write) \
         else None
-    pmc_cmd = "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --stage-reps 2"
+    pmc_cmd = "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-other-workloads --stage-reps 2"
     t = [f"kernel: {kernel}",
          f"kernel_source_sha256: {kernel_source_digest()}",
          f"workload: {wl}",
@@ -191,12 +193,12 @@ def summarise_profile(d: str, copy_bytes: int):
         npx = res["config"]["megapixels"] * 1e6
         alg = {f"normalise_kernel<{prec_code}>": npx * (STORE_BYTES[res["config"]["intermediate"]] + 4)}
         t += ["", "Other kernels, same passes and scaling (MB per dispatch; algorithmic bytes where the "
-                  "benchmark states them per kernel). The split's count grows from step to step; "
-                  "`las_split_kernel` runs both the plain split and the full-record split (feature rows and "
-                  "moments), hence its range:", "",
+                  "benchmark states them per kernel). The plain split and the full-record split (feature rows and "
+                  "moments) are separate kernels:", "",
               "| Kernel | Dispatches | Fetch | Write | Traffic | Algorithmic |", "|---|---|---|---|---|---|"]
         for k in (f"normalise_kernel<{prec_code}>", f"median_select_kernel<{prec_code}>", "las_count_kernel",
-                  "las_scan_kernel", "las_split_kernel", "sel_scatter_kernel", "sel_compact_kernel",
+                  "las_scan_kernel", "las_split_kernel", "las_split_full_kernel", "sel_scatter_kernel",
+                  "sel_compact_kernel",
                   "sel_hist_kernel", "sel_mask_kernel"):
             fv = [float(r["Counter_Value"]) * 1024 * f_fetch for r in fetch_rows
                   if k in r["Kernel_Name"] and r["Counter_Name"] == "FETCH_SIZE"]
