@@ -284,10 +284,10 @@ struct StripCtx {
   uint32_t permA[3], permB[3];     // byte selectors that put the window's mirrored
                                    // pixels in lane order (edge strips)
   int soff[4];                     // byte offsets of the lane's mirrored columns
-  int store_off[4];                // byte offset of output pixel i in its map row, or
-                                   // past the row's end (dropped) if not an output
+  int store_off;                   // byte offset of the lane's 4 values in a stored row of
+                                   // the strip, or past its end (dropped): halo lanes
   bool out_px[4];                  // pixel i is an output of this strip
-  uint8_t* map;                    // this view's map
+  uint8_t* map;                    // this strip's rows of the stored map
 };
 
 // Offset past any map row: buffer accesses beyond a descriptor's size are
@@ -308,7 +308,7 @@ __device__ __forceinline__ Lane12 fetch_row(const StripCtx& C, int yy) {
   else return load_lane(row, C.win_off);
 }
 
-template <int PREC, bool NARROW, bool ALIGNED, int P, int MS, int CPOL>
+template <int PREC, bool NARROW, int P, int MS, int CPOL>
 __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int t, uint32_t* hist) {
   using St = Store<PREC>;
   constexpr int Q = P ^ 1;             // previous row's parity slot
@@ -407,31 +407,23 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
     const float v = St::kSquare ? m : __builtin_amdgcn_sqrtf(m) * kStoreScaleRoot;
     q[i] = kept[i] ? v : 0.0f;
   }
+  // one aligned store per lane and row into the strip's stored row c, which
+  // the wavefront's 64 lanes fill whole (rows outside the strip's outputs get
+  // an empty descriptor: dropped)
   const __amdgpu_buffer_rsrc_t mrow =
-      buffer_rsrc(C.map + (int64_t)max(c, 0) * C.W * ES, row_out ? C.W * ES : 0);
+      buffer_rsrc(C.map + (int64_t)max(c, 0) * (kSlotPitch * ES), row_out ? kSlotPitch * ES : 0);
   uint32_t bits[4];  // words whose high halves are the histogram keys
   if constexpr (PREC == IGSP_FP32) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) bits[i] = __float_as_uint(q[i]);
-    if constexpr (ALIGNED) {
-      __builtin_amdgcn_raw_buffer_store_b128(u32x4{bits[0], bits[1], bits[2], bits[3]}, mrow, C.store_off[0], 0, CPOL);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) __builtin_amdgcn_raw_buffer_store_b32(bits[i], mrow, C.store_off[i], 0, CPOL);
-    }
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{bits[0], bits[1], bits[2], bits[3]}, mrow, C.store_off, 0, CPOL);
   } else {
     const uint32_t w0 = St::pack2(q[0], q[1]), w1 = St::pack2(q[2], q[3]);
     bits[0] = w0 << 16;
     bits[1] = w0;
     bits[2] = w1 << 16;
     bits[3] = w1;
-    if constexpr (ALIGNED) {
-      __builtin_amdgcn_raw_buffer_store_b64(u32x2{w0, w1}, mrow, C.store_off[0], 0, CPOL);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(bits[i] >> 16), mrow, C.store_off[i], 0, CPOL);
-    }
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2{w0, w1}, mrow, C.store_off, 0, CPOL);
     if constexpr (PREC == IGSP_FP16) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) bits[i] = __float_as_uint(St::widen((uint16_t)(bits[i] >> 16)));
@@ -460,7 +452,7 @@ __device__ __forceinline__ void strip_row(const StripCtx& C, StripState& S, int 
     }
 }
 
-template <int PREC, bool NARROW, bool ALIGNED, int CPOL>
+template <int PREC, bool NARROW, int CPOL>
 __device__ __forceinline__ void march(const StripCtx& C, uint32_t* hist) {
   StripState S = {};
   S.rows[0] = fetch_row<NARROW>(C, C.ys - kHalo);
@@ -468,12 +460,12 @@ __device__ __forceinline__ void march(const StripCtx& C, uint32_t* hist) {
   // exit inside the body: rows past the strip's last one (up to five) are
   // computed and neither stored nor counted
   for (int t = 0; t < C.T; t += 6) {
-    strip_row<PREC, NARROW, ALIGNED, 0, 0, CPOL>(C, S, t, hist);
-    strip_row<PREC, NARROW, ALIGNED, 1, 1, CPOL>(C, S, t + 1, hist);
-    strip_row<PREC, NARROW, ALIGNED, 0, 2, CPOL>(C, S, t + 2, hist);
-    strip_row<PREC, NARROW, ALIGNED, 1, 0, CPOL>(C, S, t + 3, hist);
-    strip_row<PREC, NARROW, ALIGNED, 0, 1, CPOL>(C, S, t + 4, hist);
-    strip_row<PREC, NARROW, ALIGNED, 1, 2, CPOL>(C, S, t + 5, hist);
+    strip_row<PREC, NARROW, 0, 0, CPOL>(C, S, t, hist);
+    strip_row<PREC, NARROW, 1, 1, CPOL>(C, S, t + 1, hist);
+    strip_row<PREC, NARROW, 0, 2, CPOL>(C, S, t + 2, hist);
+    strip_row<PREC, NARROW, 1, 0, CPOL>(C, S, t + 3, hist);
+    strip_row<PREC, NARROW, 0, 1, CPOL>(C, S, t + 4, hist);
+    strip_row<PREC, NARROW, 1, 2, CPOL>(C, S, t + 5, hist);
   }
 }
 
@@ -491,7 +483,8 @@ __device__ __forceinline__ void wave_strip(const EdgeLaunch& L, const ViewDesc& 
   C.T = (ye - ys) + 2 * kHalo;
   C.img = L.images + vd.in_off;
   C.pitch = 3 * (int64_t)vd.W;
-  C.map = reinterpret_cast<uint8_t*>(reinterpret_cast<typename St::T*>(L.map) + vd.map_off);
+  C.map = reinterpret_cast<uint8_t*>(reinterpret_cast<typename St::T*>(L.map) + vd.map_off +
+                                     (int64_t)(x0 / kStripCols) * vd.strip_rows * kSlotPitch);
   const int cx0 = x0 - kHalo + kLanePx * lane;            // first input column of the lane
   int sc[4];
 #pragma unroll
@@ -537,14 +530,13 @@ __device__ __forceinline__ void wave_strip(const EdgeLaunch& L, const ViewDesc& 
   const bool narrow = C.W < 4;
   C.remap = !narrow && __builtin_amdgcn_ballot_w64(!ident) != 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    C.out_px[i] = lane >= 1 && lane <= 62 && cx0 + i < C.W;
-    C.store_off[i] = C.out_px[i] ? (cx0 + i) * ES : kDropOffset;
-  }
-  const bool aligned = (C.W & 3) == 0;  // then a lane's 4 outputs are all in or all out
-  if (narrow) march<PREC, true, false, CPOL>(C, hist);
-  else if (aligned) march<PREC, false, true, CPOL>(C, hist);
-  else march<PREC, false, false, CPOL>(C, hist);
+  for (int i = 0; i < 4; ++i) C.out_px[i] = lane >= 1 && lane <= 62 && cx0 + i < C.W;
+  // lanes 1..62 store the strip's 248 columns at slot positions 0..247 (also
+  // past the view's right edge, where the values are never read); the halo
+  // lanes 63 and 0 fill positions 248..255, which nothing reads
+  C.store_off = ((lane + 63) & 63) * kLanePx * ES;
+  if (narrow) march<PREC, true, CPOL>(C, hist);
+  else march<PREC, false, CPOL>(C, hist);
 }
 
 template <int PREC, int NW>
@@ -642,50 +634,100 @@ __global__ __launch_bounds__(256) void median_select_kernel(EdgeLaunch L, int v0
   for (int j = 0; j < PER; ++j) h[b0 + j] = 0;  // ready for the next call
 }
 
-template <int PREC>
-__device__ __forceinline__ void load8(const typename Store<PREC>::T* m, int64_t p, float v[8]) {
+// ------------------------------------------------------------- element-wise walk
+//
+// The refinement and normalisation passes walk a chunk slot by slot: a
+// slot is one strip's stored row (248 values used). A wavefront takes whole slots,
+// lane l the 4 pixels at columns 248 s + 4 l .. + 3 (lanes 62 and 63 idle),
+// so the slot's index arithmetic is wave-uniform, a wavefront reads 496
+// contiguous bytes (BF16 / FP16) and writes 992 contiguous bytes of the map.
+struct SlotAt {
+  int64_t stored;  // element of the lane's first stored value in the plan's map
+  int64_t pixel;   // flat index of the lane's first pixel in the view
+  int valid;       // pixels of the lane inside the view (<= 0: none)
+};
+
+// The strips of a view (248 columns each).
+__device__ __forceinline__ int strips_of(const ViewDesc& vd) { return (vd.W + kStripCols - 1) / kStripCols; }
+
+// Slot u of a view (row u / strips, strip u % strips), lane `lane`.
+__device__ __forceinline__ SlotAt view_slot(const ViewDesc& vd, int ns, int u, int lane) {
+  const int c = __builtin_amdgcn_readfirstlane(u / ns);
+  const int s = u - c * ns;
+  const int l = min(lane, kStripGroups - 1);  // idle lanes read lane 61's values
+  SlotAt a;
+  a.stored = vd.map_off + ((int64_t)s * vd.strip_rows + c) * kSlotPitch + kLanePx * l;
+  a.pixel = (int64_t)c * vd.W + kStripCols * s + kLanePx * lane;
+  a.valid = lane < kStripGroups ? vd.W - (kStripCols * s + kLanePx * lane) : 0;
+  return a;
+}
+
+// The 4 stored values at element e, widened to float32. COHERENT reads them
+// device-coherently (agent-scope relaxed loads, i.e. with the SC1 bit): the
+// persistent form reads values other work-groups of the same launch wrote.
+template <int PREC, bool COHERENT>
+__device__ __forceinline__ void load4(const EdgeLaunch& L, int64_t e, float v[4]) {
   using S = Store<PREC>;
   if constexpr (PREC == IGSP_FP32) {
-    const f32x4 a = *as_global(reinterpret_cast<const f32x4*>(m + p));
-    const f32x4 b = *as_global(reinterpret_cast<const f32x4*>(m + p + 4));
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    uint64_t* p = reinterpret_cast<uint64_t*>(reinterpret_cast<float*>(L.map) + e);
+    uint64_t x, y;
+    if constexpr (COHERENT) {
+      x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      y = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const u32x4 q = *as_global(reinterpret_cast<const u32x4*>(p));
+      x = q.x | ((uint64_t)q.y << 32);
+      y = q.z | ((uint64_t)q.w << 32);
+    }
+    v[0] = __uint_as_float((uint32_t)x);
+    v[1] = __uint_as_float((uint32_t)(x >> 32));
+    v[2] = __uint_as_float((uint32_t)y);
+    v[3] = __uint_as_float((uint32_t)(y >> 32));
   } else {
-    const u32x4 q = *as_global(reinterpret_cast<const u32x4*>(m + p));
-    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+    uint64_t* p = reinterpret_cast<uint64_t*>(reinterpret_cast<uint16_t*>(L.map) + e);
+    uint64_t x;
+    if constexpr (COHERENT) x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else x = *as_global(p);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[2 * k] = S::widen((uint16_t)(w[k] & 0xFFFF));
-      v[2 * k + 1] = S::widen((uint16_t)(w[k] >> 16));
+    for (int i = 0; i < 4; ++i) v[i] = S::widen((uint16_t)(x >> (16 * i)));
+  }
+}
+
+// Digit histogram (into LDS) of a chunk's survivors inside the resolved
+// bucket of the radix selection, by the NW wavefronts of a work-group.
+template <int PREC, int NW, bool COHERENT>
+__device__ __forceinline__ void refine_slots(const EdgeLaunch& L, const ViewDesc& vd, const RowChunk& ck,
+                                             const MedState& st, int digit_bits, uint32_t* hs, int lane, int wave) {
+  const int ns = strips_of(vd);
+  const int dshift = st.shift - digit_bits;
+  const uint32_t dmask = (1u << digit_bits) - 1u;
+  for (int u = ck.u0 + wave; u < ck.u1; u += NW) {
+    const SlotAt a = view_slot(vd, ns, u, lane);
+    float v[4];
+    load4<PREC, COHERENT>(L, a.stored, v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t bits = __float_as_uint(v[i]);
+      if (i < a.valid && v[i] > 0.0f && (bits >> st.shift) == st.prefix)
+        atomicAdd(&hs[(bits >> dshift) & dmask], 1u);
     }
   }
 }
 
 template <int PREC>
-__global__ __launch_bounds__(256) void median_refine_kernel(EdgeLaunch L, int flat0, int digit_bits) {
+__global__ __launch_bounds__(256) void median_refine_kernel(EdgeLaunch L, int chunk0, int digit_bits) {
   __shared__ uint32_t hs[kRefineBins];
-  const FlatItem it = L.flat[flat0 + blockIdx.x];
-  const MedState st = L.state[it.view];
-  const ViewDesc vd = L.views[it.view];
+  const RowChunk ck = L.chunks[chunk0 + blockIdx.x];
+  const MedState st = L.state[ck.view];
+  const ViewDesc vd = L.views[ck.view];
   hs[threadIdx.x] = 0;
   __syncthreads();
-  if (st.n > 0 && st.shift > final_shift(PREC)) {
-    const int dshift = st.shift - digit_bits;
-    const uint32_t dmask = (1u << digit_bits) - 1u;
-    const typename Store<PREC>::T* m = reinterpret_cast<const typename Store<PREC>::T*>(L.map) + vd.map_off;
-    for (int64_t p = it.p0 + 8 * threadIdx.x; p < it.p1; p += 8 * 256) {
-      float v[8];
-      load8<PREC>(m, p, v);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const uint32_t bits = __float_as_uint(v[i]);
-        if (p + i < it.p1 && v[i] > 0.0f && (bits >> st.shift) == st.prefix)
-          atomicAdd(&hs[(bits >> dshift) & dmask], 1u);
-      }
-    }
-  }
+  if (st.n > 0 && st.shift > final_shift(PREC))
+    refine_slots<PREC, 4, false>(L, vd, ck, st, digit_bits, hs, __lane_id(),
+                                 __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
   __syncthreads();
   const uint32_t c = hs[threadIdx.x];
-  if (c) atomicAdd(&L.rhist[(int64_t)it.view * kRefineBins + threadIdx.x], c);
+  if (c) atomicAdd(&L.rhist[(int64_t)ck.view * kRefineBins + threadIdx.x], c);
 }
 
 __global__ __launch_bounds__(256) void refine_select_kernel(EdgeLaunch L, int v0, int digit_bits) {
@@ -710,86 +752,67 @@ __global__ __launch_bounds__(256) void refine_select_kernel(EdgeLaunch L, int v0
 // ------------------------------------------------------------- stage 3
 
 template <int PREC>
-__device__ __forceinline__ void normalise8(const float v[8], float med, float inv, float e[8]) {
+__device__ __forceinline__ void normalise4(const float v[4], float med, float inv, float e[4]) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < 4; ++i) {
     // the stored median itself maps to exactly 1
     const float r = v[i] == med ? 1.0f : v[i] * inv;
     e[i] = v[i] > 0.0f ? (Store<PREC>::kSquare ? __builtin_amdgcn_sqrtf(r) : r) : 0.0f;
   }
 }
 
-// Element-wise normalisation of one flat chunk of a view. Buffer descriptors
-// over the chunk take the bounds checks: each thread keeps kNormUnroll groups
-// of 8 stored values in flight, and groups past the chunk read 0 and store
-// nothing. The chunk's last, partial group (a view's pixel count need not be
-// a multiple of 8) is written again element by element at the end.
+// Normalisation of one row chunk by NW wavefronts. Each wavefront keeps
+// kNormUnroll slots' loads in flight (slots past the chunk's end load the
+// last slot again and store nothing). The chunk's output pixels are one
+// contiguous range of the map; a buffer descriptor over it takes a lane's
+// four values in one 16-byte store, and the last lane of a row whose width is
+// not a multiple of 4 stores its pixels one by one (a fourth value would land
+// on the next row).
 constexpr int kNormUnroll = 4;
 
-template <int PREC>
-__device__ __forceinline__ void load8_buf(__amdgpu_buffer_rsrc_t base, int p, float v[8]) {
-  using S = Store<PREC>;
-  if constexpr (PREC == IGSP_FP32) {
-    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(base, p * 4, 0, 0);
-    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(base, p * 4 + 16, 0, 0);
-    v[0] = __uint_as_float(a.x); v[1] = __uint_as_float(a.y); v[2] = __uint_as_float(a.z);
-    v[3] = __uint_as_float(a.w); v[4] = __uint_as_float(b.x); v[5] = __uint_as_float(b.y);
-    v[6] = __uint_as_float(b.z); v[7] = __uint_as_float(b.w);
-  } else {
-    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(base, p * 2, 0, 0);
-    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+template <int PREC, int NW, bool COHERENT>
+__device__ __forceinline__ void norm_slots(const EdgeLaunch& L, const ViewDesc& vd, const RowChunk& ck, float med,
+                                           int lane, int wave) {
+  const int ns = strips_of(vd);
+  const float inv = med > 0.0f ? 1.0f / med : 0.0f;
+  // the chunk's output pixels: from its first slot's first pixel to its last
+  // slot's last
+  const int cb = ck.u0 / ns, ce = (ck.u1 - 1) / ns;
+  const int64_t p_begin = (int64_t)cb * vd.W + kStripCols * (ck.u0 - cb * ns);
+  const int64_t p_end = (int64_t)ce * vd.W + min(vd.W, kStripCols * (ck.u1 - ce * ns));
+  const __amdgpu_buffer_rsrc_t out = buffer_rsrc(L.out + vd.out_off + p_begin, (int)(4 * (p_end - p_begin)));
+  for (int u0 = ck.u0 + wave; u0 < ck.u1; u0 += kNormUnroll * NW) {
+    SlotAt a[kNormUnroll];
+    float v[kNormUnroll][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[2 * k] = S::widen((uint16_t)(w[k] & 0xFFFF));
-      v[2 * k + 1] = S::widen((uint16_t)(w[k] >> 16));
+    for (int k = 0; k < kNormUnroll; ++k) {
+      a[k] = view_slot(vd, ns, min(u0 + k * NW, ck.u1 - 1), lane);
+      load4<PREC, COHERENT>(L, a[k].stored, v[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kNormUnroll; ++k) {
+      if (u0 + k * NW >= ck.u1) break;
+      float e[4];
+      normalise4<PREC>(v[k], med, inv, e);
+      const int off = 4 * (int)(a[k].pixel - p_begin);
+      if (a[k].valid >= kLanePx) {
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(e[0]), __float_as_uint(e[1]),
+                                                     __float_as_uint(e[2]), __float_as_uint(e[3])},
+                                               out, off, 0, 0);
+      } else {
+        for (int i = 0; i < a[k].valid; ++i)
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(e[i]), out, off + 4 * i, 0, 0);
+      }
     }
   }
 }
 
 template <int PREC>
-__global__ __launch_bounds__(256) void normalise_kernel(EdgeLaunch L, int flat0) {
-  using T = typename Store<PREC>::T;
-  constexpr int STEP = 8 * 256;
-  const FlatItem it = L.flat[flat0 + blockIdx.x];
-  const ViewDesc vd = L.views[it.view];
-  const float med = L.state[it.view].med;
-  const float inv = med > 0.0f ? 1.0f / med : 0.0f;
-  const int n = (int)(it.p1 - it.p0);
-  const int n8 = (n + 7) & ~7;  // the view's map region is padded to 64 elements
-  const __amdgpu_buffer_rsrc_t in =
-      buffer_rsrc(reinterpret_cast<const T*>(L.map) + vd.map_off + it.p0, n8 * (int)sizeof(T));
-  float* outp = L.out + vd.out_off + it.p0;
-  const __amdgpu_buffer_rsrc_t out = buffer_rsrc(outp, n * 4);
-  for (int p0 = 8 * threadIdx.x; p0 < n; p0 += kNormUnroll * STEP) {
-    float v[kNormUnroll][8];
-#pragma unroll
-    for (int u = 0; u < kNormUnroll; ++u) load8_buf<PREC>(in, p0 + u * STEP, v[u]);
-#pragma unroll
-    for (int u = 0; u < kNormUnroll; ++u) {
-      float e[8];
-      normalise8<PREC>(v[u], med, inv, e);
-      const int p = p0 + u * STEP;
-      __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(e[0]), __float_as_uint(e[1]),
-                                                   __float_as_uint(e[2]), __float_as_uint(e[3])},
-                                             out, p * 4, 0, 0);
-      __builtin_amdgcn_raw_buffer_store_b128(u32x4{__float_as_uint(e[4]), __float_as_uint(e[5]),
-                                                   __float_as_uint(e[6]), __float_as_uint(e[7])},
-                                             out, p * 4 + 16, 0, 0);
-    }
-  }
-  if (n & 7) {  // the partial last group, element by element
-    const int p = n & ~7;
-    if (threadIdx.x < n - p) {
-      float v[8], e[8];
-      load8_buf<PREC>(in, p, v);
-      normalise8<PREC>(v, med, inv, e);
-      const int k = threadIdx.x;
-      float ek = e[0];
-#pragma unroll
-      for (int i = 1; i < 8; ++i) ek = k == i ? e[i] : ek;
-      as_global(outp)[p + k] = ek;
-    }
-  }
+__global__ __launch_bounds__(256) void normalise_kernel(EdgeLaunch L, int chunk0) {
+  const RowChunk ck = L.chunks[chunk0 + blockIdx.x];
+  const ViewDesc vd = L.views[ck.view];
+  norm_slots<PREC, 4, false>(L, vd, ck, L.state[ck.view].med, __lane_id(),
+                             __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
 }
 
 // ------------------------------------------------------------- unfused form
@@ -875,7 +898,10 @@ __global__ __launch_bounds__(kUfCols) void uf_nms_kernel(EdgeLaunch L, UfLaunch 
   if (x < vd.W) {
     const int xl = refl(x - 1, vd.W), xr = refl(x + 1, vd.W);
     const float* M = U.mag + vd.map_off;
-    typename St::T* out = reinterpret_cast<typename St::T*>(L.map) + vd.map_off;
+    // this column's place in the stored map: strip x / 248, offset x % 248
+    const int sx = x / kStripCols;
+    typename St::T* out = reinterpret_cast<typename St::T*>(L.map) + vd.map_off +
+                          (int64_t)sx * vd.strip_rows * kSlotPitch + (x - kStripCols * sx);
     const int y1 = min(it.y0 + kUfRows, vd.H);
     for (int y = it.y0; y < y1; ++y) {
       const float* ru = M + (int64_t)refl(y - 1, vd.H) * vd.W;
@@ -893,11 +919,11 @@ __global__ __launch_bounds__(kUfCols) void uf_nms_kernel(EdgeLaunch L, UfLaunch 
       const float q = keep ? v : 0.0f;
       uint32_t bits;
       if constexpr (PREC == IGSP_FP32) {
-        out[(int64_t)y * vd.W + x] = q;
+        out[(int64_t)y * kSlotPitch] = q;
         bits = __float_as_uint(q);
       } else {
         const uint16_t h = (uint16_t)(St::pack2(q, 0.0f) & 0xFFFFu);
-        out[(int64_t)y * vd.W + x] = h;
+        out[(int64_t)y * kSlotPitch] = h;
         bits = __float_as_uint(St::widen(h));
       }
       if (bits != 0u)
@@ -1034,40 +1060,6 @@ __device__ __forceinline__ void await(uint32_t* ready, uint32_t level, uint32_t 
   __syncthreads();
 }
 
-// Eight stored values at element p of a chunk whose first element sits at
-// `base`, through a device-coherent buffer load (p - p0 < 2^16, so the byte
-// offset fits the descriptor).
-template <int PREC>
-__device__ __forceinline__ void load8_coherent(__amdgpu_buffer_rsrc_t base, int off, float v[8]) {
-  using S = Store<PREC>;
-  if constexpr (PREC == IGSP_FP32) {
-    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(base, off * 4, 0, kCpolAgent);
-    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(base, off * 4 + 16, 0, kCpolAgent);
-    v[0] = __uint_as_float(a.x); v[1] = __uint_as_float(a.y); v[2] = __uint_as_float(a.z);
-    v[3] = __uint_as_float(a.w); v[4] = __uint_as_float(b.x); v[5] = __uint_as_float(b.y);
-    v[6] = __uint_as_float(b.z); v[7] = __uint_as_float(b.w);
-  } else {
-    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(base, off * 2, 0, kCpolAgent);
-    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[2 * k] = S::widen((uint16_t)(w[k] & 0xFFFF));
-      v[2 * k + 1] = S::widen((uint16_t)(w[k] >> 16));
-    }
-  }
-}
-
-// Descriptor over the stored values of a flat chunk [p0, p1), rounded up to
-// whole groups of 8 (inside the view's padded region).
-template <int PREC>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const EdgeLaunch& L, const ViewDesc& vd,
-                                                             const FlatItem& it) {
-  using T = typename Store<PREC>::T;
-  const T* m = reinterpret_cast<const T*>(L.map) + vd.map_off + it.p0;
-  const int n8 = (int)((it.p1 - it.p0 + 7) & ~int64_t(7));
-  return buffer_rsrc(m, n8 * (int)sizeof(T));
-}
-
 // The thread index as a value the compiler cannot prove loop-invariant, for
 // the task functions of the persistent kernel: addresses built from it are
 // then recomputed inside each task instead of being held in registers across
@@ -1149,68 +1141,31 @@ __device__ void select_refine(const EdgeLaunch& L, int v, int digit_bits, uint32
     if (b0 + j < kRefineBins) st_agent(h + b0 + j, 0u);
 }
 
-// Digit histogram of one flat chunk for refinement pass `digit_bits`.
+// Digit histogram of one row chunk for refinement pass `digit_bits`.
 template <int PREC, int NW>
-__device__ void refine_chunk(const EdgeLaunch& L, const FlatItem& it, const MedState& st, int digit_bits,
+__device__ void refine_chunk(const EdgeLaunch& L, const RowChunk& ck, const MedState& st, int digit_bits,
                              uint32_t* hs) {
   constexpr int NT = NW * 64;
   const int tid = task_tid();
   for (int i = tid; i < kRefineBins; i += NT) hs[i] = 0;
   __syncthreads();
   if (st.n > 0 && st.shift > final_shift(PREC)) {
-    const ViewDesc vd = L.views[it.view];
-    const int dshift = st.shift - digit_bits;
-    const uint32_t dmask = (1u << digit_bits) - 1u;
-    const __amdgpu_buffer_rsrc_t mr = chunk_rsrc<PREC>(L, vd, it);
-    const int n = (int)(it.p1 - it.p0);
-    for (int p = 8 * tid; p < n; p += 8 * NT) {
-      float v[8];
-      load8_coherent<PREC>(mr, p, v);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const uint32_t bits = __float_as_uint(v[i]);
-        if (p + i < n && v[i] > 0.0f && (bits >> st.shift) == st.prefix)
-          atomicAdd(&hs[(bits >> dshift) & dmask], 1u);
-      }
-    }
+    const ViewDesc vd = L.views[ck.view];
+    refine_slots<PREC, NW, true>(L, vd, ck, st, digit_bits, hs, tid & 63, __builtin_amdgcn_readfirstlane(tid >> 6));
   }
   __syncthreads();
   for (int i = tid; i < kRefineBins; i += NT) {
     const uint32_t c = hs[i];
-    if (c) atomicAdd(&L.rhist[(int64_t)it.view * kRefineBins + i], c);
+    if (c) atomicAdd(&L.rhist[(int64_t)ck.view * kRefineBins + i], c);
   }
 }
 
-// Normalisation of one flat chunk.
+// Normalisation of one row chunk.
 template <int PREC, int NW>
-__device__ void norm_chunk(const EdgeLaunch& L, const FlatItem& it, float med) {
-  constexpr int NT = NW * 64, STEP = 8 * NT;
-  const ViewDesc vd = L.views[it.view];
-  const float inv = med > 0.0f ? 1.0f / med : 0.0f;
-  const __amdgpu_buffer_rsrc_t mr = chunk_rsrc<PREC>(L, vd, it);
-  gptr<float> out = as_global(L.out + vd.out_off + it.p0);
-  const bool aligned = ((vd.out_off + it.p0) & 3) == 0;
-  const int n = (int)(it.p1 - it.p0);
-  for (int p0 = 8 * task_tid(); p0 < n; p0 += kNormUnroll * STEP) {
-    float v[kNormUnroll][8];
-#pragma unroll
-    for (int u = 0; u < kNormUnroll; ++u) load8_coherent<PREC>(mr, p0 + u * STEP, v[u]);  // past the end: 0
-#pragma unroll
-    for (int u = 0; u < kNormUnroll; ++u) {
-      const int p = p0 + u * STEP;
-      if (p >= n) break;
-      float e[8];
-      normalise8<PREC>(v[u], med, inv, e);
-      if (aligned && p + 8 <= n) {
-        *(gptr<f32x4>)(out + p) = f32x4{e[0], e[1], e[2], e[3]};
-        *(gptr<f32x4>)(out + p + 4) = f32x4{e[4], e[5], e[6], e[7]};
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if (p + i < n) out[p + i] = e[i];
-      }
-    }
-  }
+__device__ void norm_chunk(const EdgeLaunch& L, const RowChunk& ck, float med) {
+  const ViewDesc vd = L.views[ck.view];
+  const int tid = task_tid();
+  norm_slots<PREC, NW, true>(L, vd, ck, med, tid & 63, __builtin_amdgcn_readfirstlane(tid >> 6));
 }
 
 __device__ __forceinline__ int refine_digit_bits(int prec) { return prec == IGSP_FP16 ? 3 : 8; }
@@ -1262,18 +1217,18 @@ edge_persistent_kernel(EdgeLaunch L, PersistLaunch P) {
         acq_view = v;
         acq_level = need;
       }
-      const FlatItem it = L.flat[tk.idx];
+      const RowChunk ck = L.chunks[tk.idx];
       const MedState st = load_state(L.state + v);
       if (tk.type == kTaskRefine) {
         const int db = refine_digit_bits(PREC);
-        refine_chunk<PREC, NW>(L, it, st, db, lds);
-        if (arrive<NW>(&sy->left[tk.phase], sy->n_flat, &s_flag)) {
+        refine_chunk<PREC, NW>(L, ck, st, db, lds);
+        if (arrive<NW>(&sy->left[tk.phase], sy->n_chunks, &s_flag)) {
           select_refine<NW>(L, v, db, tmp);
           publish(&sy->ready, need + 1u);
         }
       } else {
-        norm_chunk<PREC, NW>(L, it, st.med);
-        if (arrive<NW>(&sy->left[tk.phase], sy->n_flat, &s_flag) && threadIdx.x == 0) st_agent(&sy->ready, 0u);
+        norm_chunk<PREC, NW>(L, ck, st.med);
+        if (arrive<NW>(&sy->left[tk.phase], sy->n_chunks, &s_flag) && threadIdx.x == 0) st_agent(&sy->ready, 0u);
       }
     }
     __syncthreads();
@@ -1387,17 +1342,17 @@ hipError_t launch_median_select(const EdgeLaunch& L, int v0, int nv, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_median_refine(const EdgeLaunch& L, int flat0, int n_flat, int digit_bits, hipStream_t s) {
-  if (n_flat <= 0) return hipSuccess;
+hipError_t launch_median_refine(const EdgeLaunch& L, int chunk0, int n_chunks, int digit_bits, hipStream_t s) {
+  if (n_chunks <= 0) return hipSuccess;
   switch (L.precision) {
     case IGSP_FP16:
-      hipLaunchKernelGGL(median_refine_kernel<IGSP_FP16>, dim3(n_flat), dim3(256), 0, s, L, flat0, digit_bits);
+      hipLaunchKernelGGL(median_refine_kernel<IGSP_FP16>, dim3(n_chunks), dim3(256), 0, s, L, chunk0, digit_bits);
       break;
     case IGSP_BF16:
-      hipLaunchKernelGGL(median_refine_kernel<IGSP_BF16>, dim3(n_flat), dim3(256), 0, s, L, flat0, digit_bits);
+      hipLaunchKernelGGL(median_refine_kernel<IGSP_BF16>, dim3(n_chunks), dim3(256), 0, s, L, chunk0, digit_bits);
       break;
     default:
-      hipLaunchKernelGGL(median_refine_kernel<IGSP_FP32>, dim3(n_flat), dim3(256), 0, s, L, flat0, digit_bits);
+      hipLaunchKernelGGL(median_refine_kernel<IGSP_FP32>, dim3(n_chunks), dim3(256), 0, s, L, chunk0, digit_bits);
       break;
   }
   return hipGetLastError();
@@ -1410,12 +1365,12 @@ hipError_t launch_refine_select(const EdgeLaunch& L, int v0, int nv, int digit_b
   return hipGetLastError();
 }
 
-hipError_t launch_normalise(const EdgeLaunch& L, int flat0, int n_flat, hipStream_t s) {
-  if (n_flat <= 0) return hipSuccess;
+hipError_t launch_normalise(const EdgeLaunch& L, int chunk0, int n_chunks, hipStream_t s) {
+  if (n_chunks <= 0) return hipSuccess;
   switch (L.precision) {
-    case IGSP_FP16: hipLaunchKernelGGL(normalise_kernel<IGSP_FP16>, dim3(n_flat), dim3(256), 0, s, L, flat0); break;
-    case IGSP_BF16: hipLaunchKernelGGL(normalise_kernel<IGSP_BF16>, dim3(n_flat), dim3(256), 0, s, L, flat0); break;
-    default: hipLaunchKernelGGL(normalise_kernel<IGSP_FP32>, dim3(n_flat), dim3(256), 0, s, L, flat0); break;
+    case IGSP_FP16: hipLaunchKernelGGL(normalise_kernel<IGSP_FP16>, dim3(n_chunks), dim3(256), 0, s, L, chunk0); break;
+    case IGSP_BF16: hipLaunchKernelGGL(normalise_kernel<IGSP_BF16>, dim3(n_chunks), dim3(256), 0, s, L, chunk0); break;
+    default: hipLaunchKernelGGL(normalise_kernel<IGSP_FP32>, dim3(n_chunks), dim3(256), 0, s, L, chunk0); break;
   }
   return hipGetLastError();
 }

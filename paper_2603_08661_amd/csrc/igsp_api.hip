@@ -20,8 +20,10 @@
 namespace igsp {
 namespace {
 
-constexpr int kFlatChunk = 4096;  // pixels per work-group of the element-wise passes (measured best)
-constexpr int kPersistChunk = 65536;  // pixels per element-wise task of the persistent form
+// Slots (248 pixels each) per work-group of the element-wise passes, about
+// 4 Ki pixels (measured best), and per element-wise task of the persistent form.
+constexpr int kChunkSlots = 16;
+constexpr int kPersistChunkSlots = 264;
 // Distance, in tasks, between a view's phases in the persistent task list, as
 // a multiple of the resident work-groups: a task handed out that many
 // positions later finds the earlier phase finished.
@@ -81,15 +83,15 @@ struct EdgePlan {
   ViewDesc* d_views = nullptr;
   EdgeItem* d_items = nullptr;
   EdgeItem* d_items_all = nullptr;  // the same items in the order of a launch over every view
-  FlatItem* d_flat = nullptr;
-  std::vector<int> item_begin, flat_begin;  // per view, size n_views + 1
+  RowChunk* d_chunks = nullptr;
+  std::vector<int> item_begin, chunk_begin;  // per view, size n_views + 1
   void* d_map = nullptr;
   uint32_t* d_hist = nullptr;
   uint32_t* d_rhist = nullptr;
   MedState* d_state = nullptr;
-  // persistent form (built on first use): its own coarser flat chunks, the
+  // persistent form (built on first use): its own coarser row chunks, the
   // ordered task list, per-view phase counters and the queue
-  FlatItem* d_pflat = nullptr;
+  RowChunk* d_pchunks = nullptr;
   PTask* d_tasks = nullptr;
   PViewSync* d_sync = nullptr;
   PCtl* d_ctl = nullptr;
@@ -98,10 +100,10 @@ struct EdgePlan {
   UfLaunch uf{};
   int64_t map_elems = 0;
   ~EdgePlan() {
-    (void)hipFree(d_views); (void)hipFree(d_items); (void)hipFree(d_items_all); (void)hipFree(d_flat);
+    (void)hipFree(d_views); (void)hipFree(d_items); (void)hipFree(d_items_all); (void)hipFree(d_chunks);
     (void)hipFree(d_map);
     (void)hipFree(d_hist); (void)hipFree(d_rhist); (void)hipFree(d_state);
-    (void)hipFree(d_pflat); (void)hipFree(d_tasks); (void)hipFree(d_sync); (void)hipFree(d_ctl);
+    (void)hipFree(d_pchunks); (void)hipFree(d_tasks); (void)hipFree(d_sync); (void)hipFree(d_ctl);
     (void)hipFree(const_cast<UfItem*>(uf.items)); (void)hipFree(uf.gray); (void)hipFree(uf.blur);
     (void)hipFree(uf.mag); (void)hipFree(uf.code);
   }
@@ -212,6 +214,13 @@ void save_tune_cache() {
   std::fclose(f);
 }
 
+// Chunks of a view's slots (one strip's stored row each, 248 pixels) with
+// `slots` slots each, the last one shorter.
+void row_chunks(int v, int W, int H, int slots, std::vector<RowChunk>* out) {
+  const int64_t n = (int64_t)H * ((W + kStripCols - 1) / kStripCols);
+  for (int64_t u0 = 0; u0 < n; u0 += slots) out->push_back(RowChunk{v, (int32_t)u0, (int32_t)std::min(n, u0 + slots), 0});
+}
+
 igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) {
   auto plan = std::make_shared<EdgePlan>();
   plan->key = key;
@@ -221,24 +230,26 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
   const int esz = key.precision == IGSP_FP32 ? 4 : 2;
   std::vector<ViewDesc> vd(n);
   std::vector<EdgeItem> items;
-  std::vector<FlatItem> flat;
+  std::vector<RowChunk> chunks;
   plan->item_begin.resize(n + 1);
-  plan->flat_begin.resize(n + 1);
+  plan->chunk_begin.resize(n + 1);
   int64_t map_elems = 0;
   for (int v = 0; v < n; ++v) {
     const igsp_view& d = key.views[v];
-    vd[v] = ViewDesc{d.width, d.height, d.in_offset, d.out_offset, map_elems};
-    const int64_t npx = (int64_t)d.width * d.height;
-    map_elems += (npx + 63) / 64 * 64;
+    // the stored map, strip by strip (each strip's rows one after another,
+    // in slots of 256 values)
+    const int strips = (d.width + kStripCols - 1) / kStripCols;
+    vd[v] = ViewDesc{d.width, d.height, d.in_offset, d.out_offset, map_elems, d.height, 0};
+    map_elems += (int64_t)strips * d.height * kSlotPitch;
     plan->item_begin[v] = (int)items.size();
     for (int x0 = 0; x0 < d.width; x0 += kStripCols)
       for (int y0 = 0; y0 < d.height; y0 += band)
         items.push_back(EdgeItem{v, x0, y0, std::min(band, d.height - y0)});
-    plan->flat_begin[v] = (int)flat.size();
-    for (int64_t p = 0; p < npx; p += kFlatChunk) flat.push_back(FlatItem{v, 0, p, std::min(npx, p + kFlatChunk)});
+    plan->chunk_begin[v] = (int)chunks.size();
+    row_chunks(v, d.width, d.height, kChunkSlots, &chunks);
   }
   plan->item_begin[n] = (int)items.size();
-  plan->flat_begin[n] = (int)flat.size();
+  plan->chunk_begin[n] = (int)chunks.size();
   plan->map_elems = map_elems;
   // A launch over every view gives each XCD a contiguous eighth of the list
   // (the kernel's block remap); inside each eighth, full bands come first and
@@ -256,7 +267,7 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
   }
   if (upload(&plan->d_views, vd) != hipSuccess || upload(&plan->d_items, items) != hipSuccess ||
       upload(&plan->d_items_all, all) != hipSuccess ||
-      upload(&plan->d_flat, flat) != hipSuccess)
+      upload(&plan->d_chunks, chunks) != hipSuccess)
     return IGSP_ERR_HIP;
   if (hipMalloc(&plan->d_map, (size_t)std::max<int64_t>(map_elems, 64) * esz) != hipSuccess) return IGSP_ERR_HIP;
   const size_t hb = (size_t)n * kBinsMax * sizeof(uint32_t), rb = (size_t)n * kRefineBins * sizeof(uint32_t);
@@ -292,16 +303,14 @@ igsp_status ensure_persistent(EdgePlan* P) {
   const int per_cu = persistent_blocks_per_cu(prec, P->key.wg_waves);
   if (per_cu <= 0 || cus <= 0) return IGSP_ERR_HIP;
   P->grid = per_cu * cus;
-  std::vector<FlatItem> pflat;
-  std::vector<int> pflat_begin(n + 1);
+  std::vector<RowChunk> pchunks;
+  std::vector<int> pchunk_begin(n + 1);
   for (int v = 0; v < n; ++v) {
-    const int64_t npx = (int64_t)P->key.views[v].width * P->key.views[v].height;
-    pflat_begin[v] = (int)pflat.size();
-    for (int64_t p = 0; p < npx; p += kPersistChunk)
-      pflat.push_back(FlatItem{v, 0, p, std::min(npx, p + kPersistChunk)});
+    pchunk_begin[v] = (int)pchunks.size();
+    row_chunks(v, P->key.views[v].width, P->key.views[v].height, kPersistChunkSlots, &pchunks);
   }
-  pflat_begin[n] = (int)pflat.size();
-  const int64_t per_view = ((int64_t)P->item_begin[n] + (int64_t)(phases - 1) * pflat_begin[n]) / std::max(n, 1);
+  pchunk_begin[n] = (int)pchunks.size();
+  const int64_t per_view = ((int64_t)P->item_begin[n] + (int64_t)(phases - 1) * pchunk_begin[n]) / std::max(n, 1);
   P->lag = (int)std::min<int64_t>(std::max<int64_t>(1, ((int64_t)kLagGenerations * P->grid + per_view - 1) /
                                                            std::max<int64_t>(per_view, 1)),
                                   std::max(n, 1));
@@ -314,21 +323,21 @@ igsp_status ensure_persistent(EdgePlan* P) {
         for (int i = P->item_begin[v]; i < P->item_begin[v + 1]; ++i) tasks.push_back(PTask{kTaskStencil, v, i, 0});
       } else {
         const int type = p <= levels ? kTaskRefine : kTaskNorm;
-        for (int f = pflat_begin[v]; f < pflat_begin[v + 1]; ++f) tasks.push_back(PTask{type, v, f, p});
+        for (int f = pchunk_begin[v]; f < pchunk_begin[v + 1]; ++f) tasks.push_back(PTask{type, v, f, p});
       }
     }
   std::vector<PViewSync> sync(n);
   for (int v = 0; v < n; ++v) {
     const uint32_t ni = (uint32_t)(P->item_begin[v + 1] - P->item_begin[v]);
-    const uint32_t nf = (uint32_t)(pflat_begin[v + 1] - pflat_begin[v]);
+    const uint32_t nf = (uint32_t)(pchunk_begin[v + 1] - pchunk_begin[v]);
     sync[v] = PViewSync{{ni, nf, nf, nf}, 0u, ni, nf, 0u};
   }
   std::vector<PCtl> ctl(1, PCtl{0u, 0u, 0u, 0u});
   P->n_tasks = (int)tasks.size();
-  if (upload(&P->d_pflat, pflat) != hipSuccess || upload(&P->d_sync, sync) != hipSuccess ||
+  if (upload(&P->d_pchunks, pchunks) != hipSuccess || upload(&P->d_sync, sync) != hipSuccess ||
       upload(&P->d_ctl, ctl) != hipSuccess || upload(&P->d_tasks, tasks) != hipSuccess) {
-    (void)hipFree(P->d_pflat); (void)hipFree(P->d_sync); (void)hipFree(P->d_ctl); (void)hipFree(P->d_tasks);
-    P->d_pflat = nullptr; P->d_sync = nullptr; P->d_ctl = nullptr; P->d_tasks = nullptr;
+    (void)hipFree(P->d_pchunks); (void)hipFree(P->d_sync); (void)hipFree(P->d_ctl); (void)hipFree(P->d_tasks);
+    P->d_pchunks = nullptr; P->d_sync = nullptr; P->d_ctl = nullptr; P->d_tasks = nullptr;
     return IGSP_ERR_HIP;
   }
   return IGSP_OK;
@@ -418,7 +427,7 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
   L.out = out_maps;
   L.views = P->d_views;
   L.items = P->d_items;
-  L.flat = P->d_flat;
+  L.chunks = P->d_chunks;
   L.map = P->d_map;
   L.hist = P->d_hist;
   L.rhist = P->d_rhist;
@@ -441,7 +450,7 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
   auto mark = [&](int k, hipStream_t st) -> hipError_t { return ev ? hipEventRecord(ev[k], st) : hipSuccess; };
   // median selection (+ refinement passes) and normalisation of views [v0, v1)
   auto tail = [&](int v0, int v1, hipStream_t st) -> hipError_t {
-    const int f0 = P->flat_begin[v0], f1 = P->flat_begin[v1];
+    const int f0 = P->chunk_begin[v0], f1 = P->chunk_begin[v1];
     hipError_t e = launch_median_select(L, v0, v1 - v0, st);
     for (int db : passes) {
       if (e == hipSuccess) e = launch_median_refine(L, f0, f1 - f0, db, st);
@@ -458,7 +467,7 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
     return launch_edge_fused(L, P->item_begin[v0], P->item_begin[v1] - P->item_begin[v0], st);
   };
   auto norm = [&](int v0, int v1, hipStream_t st) -> hipError_t {
-    return launch_normalise(L, P->flat_begin[v0], P->flat_begin[v1] - P->flat_begin[v0], st);
+    return launch_normalise(L, P->chunk_begin[v0], P->chunk_begin[v1] - P->chunk_begin[v0], st);
   };
   hipError_t e = mark(0, s);
   if (e == hipSuccess && form == IGSP_BATCHED_PERSISTENT) {
@@ -481,7 +490,7 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
       PL.wait_bias = 1u << 24;
     }
     EdgeLaunch LP = L;
-    LP.flat = P->d_pflat;
+    LP.chunks = P->d_pchunks;
     e = launch_edge_persistent(LP, PL, P->grid, s);
     for (int k = 1; k < 4 && e == hipSuccess; ++k) e = mark(k, s);
   } else if (e == hipSuccess && form == IGSP_UNFUSED) {

@@ -39,11 +39,23 @@ constexpr int kBinsSquare = 58 * 128;                      // 1 .. 2^58
 constexpr int kBinsMax = kBinsSquare;
 constexpr int kRefineBins = 256;          // radix digit of the refine passes
 
+// The stored intermediate of a view is kept strip by strip: strip s (output
+// columns 248 s .. 248 s + 247) holds its rows one after another in slots of
+// 256 values (its 248 outputs and 8 unused values: one aligned 512-byte or
+// 1 KiB store per wavefront and row, whole cache lines only). Row c of strip
+// s starts at element map_off + (s * strip_rows + c) * 256, strip_rows = H.
+// Every stencil wavefront thus writes one contiguous stream and no cache line
+// is shared between two slots.
+constexpr int kStripGroups = kStripCols / kLanePx;  // 62 groups of 4 pixels
+constexpr int kSlotPitch = kWaveCols;               // 256 values per stored row
+
 struct ViewDesc {
   int32_t W, H;
-  int64_t in_off;    // bytes from `images`
-  int64_t out_off;   // floats from `out_maps`
-  int64_t map_off;   // elements from the plan's map buffer (pitch W)
+  int64_t in_off;      // bytes from `images`
+  int64_t out_off;     // floats from `out_maps`
+  int64_t map_off;     // elements from the plan's map buffer
+  int32_t strip_rows;  // rows per strip of the stored map (H)
+  int32_t pad;
 };
 
 struct EdgeItem {    // one work-group of the fused stencil kernel
@@ -53,10 +65,14 @@ struct EdgeItem {    // one work-group of the fused stencil kernel
   int32_t rows;      // output rows in the band
 };
 
-struct FlatItem {    // one work-group of an element-wise pass
+// One work-group of an element-wise pass (median refinement, normalisation):
+// slots [u0, u1) of a view, in row-major order over (row c, strip s), slot
+// u = c * strips + s. Consecutive slots cover consecutive pixels of the map,
+// so a chunk's output is one contiguous range.
+struct RowChunk {
   int32_t view;
+  int32_t u0, u1;
   int32_t pad;
-  int64_t p0, p1;    // flat pixel range [p0, p1) of the view
 };
 
 struct MedState {    // radix-select state of one view's median
@@ -74,7 +90,7 @@ struct EdgeLaunch {
   float* out;
   const ViewDesc* views;
   const EdgeItem* items;
-  const FlatItem* flat;
+  const RowChunk* chunks;
   void* map;
   uint32_t* hist;            // [n_views][kBinsMax]
   uint32_t* rhist;           // [n_views][kRefineBins]
@@ -97,7 +113,7 @@ enum : int32_t { kTaskStencil = 0, kTaskRefine = 1, kTaskNorm = 2 };
 struct PTask {
   int32_t type;
   int32_t view;
-  int32_t idx;       // stencil: index into items; refine / norm: into flat
+  int32_t idx;       // stencil: index into items; refine / norm: into chunks
   int32_t phase;     // 0 .. levels + 1
 };
 
@@ -105,8 +121,8 @@ struct PViewSync {   // per view, in device memory
   uint32_t left[4];  // tasks of each phase still running; the last one
                      // restores the count for the next launch
   uint32_t ready;    // selection steps completed (reset to 0 at the end)
-  uint32_t n_items;  // restore values: stencil items, flat chunks
-  uint32_t n_flat;
+  uint32_t n_items;  // restore values: stencil items, row chunks
+  uint32_t n_chunks;
   uint32_t pad;
 };
 
@@ -155,10 +171,10 @@ struct UfLaunch {
 // tables; view ranges are [v0, v1)).
 hipError_t launch_edge_fused(const EdgeLaunch& L, int item0, int n_items, hipStream_t s);
 hipError_t launch_median_select(const EdgeLaunch& L, int v0, int nv, hipStream_t s);
-hipError_t launch_median_refine(const EdgeLaunch& L, int flat0, int n_flat, int digit_bits, hipStream_t s);
+hipError_t launch_median_refine(const EdgeLaunch& L, int chunk0, int n_chunks, int digit_bits, hipStream_t s);
 hipError_t launch_refine_select(const EdgeLaunch& L, int v0, int nv, int digit_bits, int final_shift,
                                 hipStream_t s);
-hipError_t launch_normalise(const EdgeLaunch& L, int flat0, int n_flat, hipStream_t s);
+hipError_t launch_normalise(const EdgeLaunch& L, int chunk0, int n_chunks, hipStream_t s);
 // The stencil steps of the unfused form: gray, blur, Sobel, suppression
 // (+ histogram), four launches; the median and normalisation follow as in the
 // staged form.

@@ -3,10 +3,11 @@ VALU lane-operations per output pixel of the steady-state loop -- checked
 against the gfx950 code the compiler makes of the kernel now (no GPU: the
 kernel is compiled to assembly on the host).
 
-The loop marches six rows per iteration; an interior strip with 4-pixel
-aligned stores issues one wide store per row (BF16 / FP16: dwordx2, FP32:
-dwordx4). Edge strips run an extra block that puts mirrored columns in lane
-order; it sits behind a uniform branch and is not part of the steady state.
+The loop marches six rows per iteration and issues one 12-byte load and one
+wide store per lane and row (BF16 / FP16: dwordx2, FP32: dwordx4); views
+narrower than 4 pixels have a loop of their own that loads byte by byte.
+Edge strips run an extra block that puts mirrored columns in lane order; it
+sits behind a uniform branch and is not part of the steady state.
 Per pixel: (VALU instructions of the loop - that block) / (6 rows x 4 pixels)."""
 import os
 import re
@@ -40,6 +41,8 @@ def _loop_lane_ops_per_px(asm: str, prec: int) -> float:
         ins = [x.strip() for x in seg if x.strip() and not x.strip().startswith((".", ";"))]
         if sum(1 for x in ins if x.split()[0] == WIDE_STORE[prec]) != 6:
             continue
+        if sum(1 for x in ins if x.split()[0] == "buffer_load_dwordx3") != 6:
+            continue  # the byte-by-byte loop of views narrower than 4 pixels
         valu = sum(1 for x in ins if x.startswith("v_"))
         remap = 0
         for a, x in enumerate(seg):
