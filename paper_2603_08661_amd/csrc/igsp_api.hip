@@ -826,7 +826,9 @@ extern "C" igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view
   if (st != IGSP_OK) return st;
   if (n_views == 0) return IGSP_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  static const int kSeg[] = {32, 48, 64, 96, 128, 192, 256};
+  // segment heights whose rows plus the 8 halo rows are a multiple of the
+  // stencil loop's 6-row unroll (no row computed past a full segment's end)
+  static const int kSeg[] = {28, 40, 64, 88, 100, 124, 148, 196, 244};
   static const int kWaves[] = {1, 2, 4, 8};
   std::vector<int> forms;
   if (batched == IGSP_BATCHED) forms = {IGSP_BATCHED_STAGED, IGSP_BATCHED_PERSISTENT};
@@ -851,7 +853,7 @@ extern "C" igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view
           st = get_edge_plan(views, n_views, &o, &plan);
         }
         if (st != IGSP_OK) break;
-        const int reps = 3;
+        const int reps = 8;
         st = enqueue_edge(plan.get(), images, ext.img_end, out_maps, &o, s);  // warm-up
         if (st == IGSP_OK && hipEventRecord(e0, s) != hipSuccess) st = IGSP_ERR_HIP;
         for (int r = 0; r < reps && st == IGSP_OK; ++r)
