@@ -654,7 +654,11 @@ __device__ __forceinline__ int strips_of(const ViewDesc& vd) { return (vd.W + kS
 __device__ __forceinline__ SlotAt view_slot(const ViewDesc& vd, int ns, int u, int lane) {
   const int c = __builtin_amdgcn_readfirstlane(u / ns);
   const int s = u - c * ns;
-  const int l = min(lane, kStripGroups - 1);  // idle lanes read lane 61's values
+  // lanes with no pixel in the view (62, 63, and those past its right edge)
+  // read the last lane's values again: no cache line beyond the view's part
+  // of the slot is fetched
+  const int last = min(kStripGroups, (vd.W - kStripCols * s + kLanePx - 1) / kLanePx) - 1;
+  const int l = min(lane, last);
   SlotAt a;
   a.stored = vd.map_off + ((int64_t)s * vd.strip_rows + c) * kSlotPitch + kLanePx * l;
   a.pixel = (int64_t)c * vd.W + kStripCols * s + kLanePx * lane;
