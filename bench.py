@@ -11,9 +11,12 @@ replayed per step. The plain per-view FP32 form of the same step is timed
 beside it, the dominant kernel is timed live with HIP events on its own
 stream for the roofline, and the CPU oracle is timed on a bounded sample.
 
-Prints one JSON line. Inputs are resident in HBM before timing starts; the
-Gaussian count grows on the device from step to step (each step splits the
-same selected rows again, so every step does the same split work).
+Prints one JSON line. Inputs are resident in HBM before timing starts. The
+live Gaussian count is set back to N on the device before every step (one
+8-byte device copy inside the timed region), so every step splits the same K
+of the same N rows. The default warm-up (25 steps) outlasts the GPU's
+ramp from idle: the first ten or so steps after an idle period run up to 15%
+slower, then the step settles.
 """
 from __future__ import annotations
 
@@ -295,7 +298,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=25)
     ap.add_argument("--workload", default="step_views300_las3m", choices=sorted(synth.WORKLOADS))
     ap.add_argument("--precision", default=None, help="override the workload's intermediate storage")
     ap.add_argument("--seg-rows", type=int, default=0)
@@ -352,18 +355,18 @@ def main():
     mpx = vb.pixels / 1e6
 
     has_las = w.n_gauss > 0
-    steps_total = 2 * (args.warmup + args.steps) + args.stage_reps + 4
     if has_las:
         g = w.gaussian_set()
         mk = w.split_mask()
         N0, K = w.n_gauss, w.n_split
-        cap = N0 + K * steps_total
+        cap = N0 + K     # every split starts again from N0 (reset_count)
         G = {}
         for k in ("means", "log_scales", "quats", "opacity_logits"):
             a = getattr(g, k)
             G[k] = torch.zeros((cap,) + a.shape[1:], dtype=torch.float32, device=dev)
             G[k][:N0] = torch.from_numpy(a).to(dev)
         G["count"] = torch.tensor([N0], dtype=torch.int64, device=dev)
+        n0_dev = torch.tensor([N0], dtype=torch.int64, device=dev)
         mask = torch.zeros(cap, dtype=torch.uint8, device=dev)
         mask[:N0] = torch.from_numpy(mk).to(dev)
         sidx = torch.zeros(cap, dtype=torch.int32, device=dev)
@@ -377,7 +380,13 @@ def main():
         igsp.edge_importance(img, views, out, precision=p, batched=bform, seg_rows=args.seg_rows,
                              wg_waves=args.wg_waves, stage_events=ev, stream=stream)
 
+    def reset_count():
+        # the split grows N in place; every step starts again from the workload's N
+        with torch.cuda.stream(stream):
+            G["count"].copy_(n0_dev)
+
     def las():
+        reset_count()
         igsp.long_axis_split(G["means"], G["log_scales"], G["quats"], G["opacity_logits"], G["count"], mask,
                              sidx, status, stream=stream)
 
@@ -411,7 +420,9 @@ def main():
         with torch.cuda.stream(stream):
             step = igsp.Step(img, views, out, G, mask, sidx, status, precision=prec, batched=bform,
                              seg_rows=args.seg_rows, wg_waves=args.wg_waves, stream=stream)
-        run_primary = lambda: step.launch(stream)  # noqa: E731
+        def run_primary():
+            reset_count()
+            step.launch(stream)
         form = f"batched ({bform}) {prec} + LAS, one HIP graph per step"
     else:
         def run_primary():
