@@ -90,3 +90,48 @@ def test_scores_independent_of_entry_order_and_exact():
             if e > 0:
                 ref[gi] += int(np.floor(float(e) * 2.0 ** 32))
     assert a.tolist() == ref
+
+
+def test_fixed_point_scores_select_what_real_sums_select():
+    """How much the fixed-point reading of the score (each product rounded to
+    float32, then floored to units of 2^-32) moves the selection, against
+    scores summed in FP64 from the exact products of the stored float32
+    inputs. 200k Gaussians, 20 views of 1024 x 768 with log-normal maps (65%
+    of pixels zero), discs of radius 1-5 px, 40% candidates, K = 20%. A
+    Gaussian can change sides only if its real score lies within its own
+    rounding bound plus the K-th score's of the K-th real score; every one
+    that changes must be such a one, and there are at most a few."""
+    import synth
+
+    rng = np.random.default_rng(77)
+    nv, W, H, N = 20, 1024, 768, 200_000
+    Ws, Hs = np.full(nv, W), np.full(nv, H)
+    off = np.arange(nv, dtype=np.int64) * W * H
+    maps = rng.lognormal(0.0, 1.0, nv * W * H).astype(np.float32)
+    maps[rng.random(maps.size) < 0.65] = 0.0
+    c = synth.contributions(4242, N, Ws, Hs, 3)
+    q = oracle.split_scores(maps, Ws, Hs, off, c.gauss, c.view, c.pixel, c.weight, N)
+    # real-valued scores: FP64 products of the same float32 inputs, no rounding to float32, no floor
+    e = maps[off[c.view] + c.pixel].astype(np.float64) * c.weight.astype(np.float64)
+    real = np.bincount(c.gauss, weights=e, minlength=N)
+    # per-Gaussian bound of |q 2^-32 - real|: float32 rounding of each product (2^-24 relative)
+    # and the floor (2^-32 absolute), summed over its contributions
+    bound = np.bincount(c.gauss, weights=e * 2.0 ** -24 + 2.0 ** -32, minlength=N)
+    assert np.all(np.abs(q * 2.0 ** -32 - real) <= bound)
+    grad = synth.grad_accum(4243, N)
+    thr = float(np.quantile(grad, 0.6))
+    K = N // 5
+    budget = N + K
+    mq, kq = oracle.split_select(q, grad, N, thr, False, budget)
+    cand = grad >= np.float32(thr)
+    idx = np.flatnonzero(cand)
+    order = np.lexsort((idx, -real[idx]))
+    mr = np.zeros(N, np.uint8)
+    mr[idx[order[:K]]] = 1
+    assert kq == K
+    changed = np.flatnonzero(mq != mr)
+    t = real[idx[order[K - 1]]]                          # the K-th real score
+    bk = bound[idx[order[K - 1]]]
+    assert np.all(np.abs(real[changed] - t) <= bound[changed] + bk + 1e-300)
+    assert changed.size <= 4, changed.size
+    print(f"selection differs for {changed.size} of {N} Gaussians ({K} selected)")
