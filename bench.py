@@ -113,7 +113,7 @@ def summarise_profile(d: str, copy_bytes: int):
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     wl = res["config"]["workload"]
     tag = f"{kernel}_w{res['config']['views']}v_{res['config']['intermediate']}"
-    bench_cmd = "python3 bench.py --steps 10 --warmup 3 --no-cpu-baseline --no-other-workloads"
+    bench_cmd = "python3 bench.py --steps 10 --warmup 25 --no-cpu-baseline --no-other-workloads"
     lines = [f"# Kernel trace: {wl}", "",
              "Command (repo root, TMPDIR=/tmp):", "",
              f"    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/trace -o t -- {bench_cmd}"
