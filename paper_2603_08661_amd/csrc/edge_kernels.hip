@@ -2,8 +2,9 @@
 //
 // Stage 1, edge_fused: one pass over the 8-bit RGB input computes grayscale,
 // the binomial 5x5 blur, the Sobel gradient, the orientation bin and the
-// non-maximum suppression, writes one stored value per surviving pixel
-// (FP32, FP16 or BF16) and accumulates a per-view histogram of its top 16
+// non-maximum suppression, writes one stored value per pixel (the thinned
+// magnitude at survivors, 0 elsewhere; FP32, FP16 or BF16) into the view's
+// strip-major slots and accumulates a per-view histogram of its top 16
 // bits. The paper runs these steps as separate kernels with HBM
 // intermediates and names a shared-memory fusion as future work; here
 // nothing between the input bytes and the suppressed magnitude leaves the
@@ -17,8 +18,10 @@
 //     load, one row ahead of its use; a wave's loads cover 768 contiguous
 //     bytes. Row indices, descriptors and bounds are wave-uniform scalar
 //     work, and the loop body issues the same memory operations on every
-//     lane (stores of non-output pixels go past the descriptor's end and are
-//     dropped), so waits never drain the prefetch.
+//     lane (a wavefront's store of one row fills one 256-value slot of its
+//     strip with one aligned store per lane; rows that are not outputs get
+//     an empty descriptor and are dropped), so waits never drain the
+//     prefetch.
 //   - Gray, blur and Sobel run in exact 32-bit integers (|gx|,|gy| < 2^28).
 //     The magnitude, its orientation test and the suppression comparisons
 //     are FP32.
@@ -27,7 +30,9 @@
 // selection of the lower median of each view's stored survivor values; BF16
 // needs no refinement, FP16 one 3-bit pass, FP32 two 8-bit passes.
 // Stage 3, normalise: map = q / median (FP16) or sqrt(q / median) (FP32,
-// BF16) at survivors, 0 elsewhere.
+// BF16) at survivors, 0 elsewhere. Stages 2 and 3 walk the slots, one per
+// wavefront at a time, and stage 3 writes each chunk's row-major map range
+// with 16-byte stores.
 
 #include <hip/hip_fp16.h>
 
@@ -699,21 +704,32 @@ __device__ __forceinline__ void load4(const EdgeLaunch& L, int64_t e, float v[4]
 
 // Digit histogram (into LDS) of a chunk's survivors inside the resolved
 // bucket of the radix selection, by the NW wavefronts of a work-group.
+constexpr int kRefineUnroll = 4;
 template <int PREC, int NW, bool COHERENT>
 __device__ __forceinline__ void refine_slots(const EdgeLaunch& L, const ViewDesc& vd, const RowChunk& ck,
                                              const MedState& st, int digit_bits, uint32_t* hs, int lane, int wave) {
   const int ns = strips_of(vd);
   const int dshift = st.shift - digit_bits;
   const uint32_t dmask = (1u << digit_bits) - 1u;
-  for (int u = ck.u0 + wave; u < ck.u1; u += NW) {
-    const SlotAt a = view_slot(vd, ns, u, lane);
-    float v[4];
-    load4<PREC, COHERENT>(L, a.stored, v);
+  // kRefineUnroll slots' loads in flight per wavefront (slots past the
+  // chunk's end load the last slot again and count nothing)
+  for (int u0 = ck.u0 + wave; u0 < ck.u1; u0 += kRefineUnroll * NW) {
+    SlotAt a[kRefineUnroll];
+    float v[kRefineUnroll][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t bits = __float_as_uint(v[i]);
-      if (i < a.valid && v[i] > 0.0f && (bits >> st.shift) == st.prefix)
-        atomicAdd(&hs[(bits >> dshift) & dmask], 1u);
+    for (int k = 0; k < kRefineUnroll; ++k) {
+      a[k] = view_slot(vd, ns, min(u0 + k * NW, ck.u1 - 1), lane);
+      load4<PREC, COHERENT>(L, a[k].stored, v[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kRefineUnroll; ++k) {
+      if (u0 + k * NW >= ck.u1) break;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t bits = __float_as_uint(v[k][i]);
+        if (i < a[k].valid && v[k][i] > 0.0f && (bits >> st.shift) == st.prefix)
+          atomicAdd(&hs[(bits >> dshift) & dmask], 1u);
+      }
     }
   }
 }
