@@ -21,8 +21,11 @@ namespace igsp {
 namespace {
 
 // Slots (248 pixels each) per work-group of the element-wise passes, about
-// 4 Ki pixels (measured best), and per element-wise task of the persistent form.
+// 4 Ki pixels (measured best for normalisation), per work-group of the
+// median's refinement passes (coarser: each work-group clears and flushes a
+// histogram) and per element-wise task of the persistent form.
 constexpr int kChunkSlots = 16;
+constexpr int kRefineChunkSlots = 64;
 constexpr int kPersistChunkSlots = 264;
 // Distance, in tasks, between a view's phases in the persistent task list, as
 // a multiple of the resident work-groups: a task handed out that many
@@ -84,7 +87,8 @@ struct EdgePlan {
   EdgeItem* d_items = nullptr;
   EdgeItem* d_items_all = nullptr;  // the same items in the order of a launch over every view
   RowChunk* d_chunks = nullptr;
-  std::vector<int> item_begin, chunk_begin;  // per view, size n_views + 1
+  RowChunk* d_rchunks = nullptr;  // the refinement passes' coarser chunks
+  std::vector<int> item_begin, chunk_begin, rchunk_begin;  // per view, size n_views + 1
   void* d_map = nullptr;
   uint32_t* d_hist = nullptr;
   uint32_t* d_rhist = nullptr;
@@ -101,7 +105,7 @@ struct EdgePlan {
   int64_t map_elems = 0;
   ~EdgePlan() {
     (void)hipFree(d_views); (void)hipFree(d_items); (void)hipFree(d_items_all); (void)hipFree(d_chunks);
-    (void)hipFree(d_map);
+    (void)hipFree(d_rchunks); (void)hipFree(d_map);
     (void)hipFree(d_hist); (void)hipFree(d_rhist); (void)hipFree(d_state);
     (void)hipFree(d_pchunks); (void)hipFree(d_tasks); (void)hipFree(d_sync); (void)hipFree(d_ctl);
     (void)hipFree(const_cast<UfItem*>(uf.items)); (void)hipFree(uf.gray); (void)hipFree(uf.blur);
@@ -230,9 +234,10 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
   const int esz = key.precision == IGSP_FP32 ? 4 : 2;
   std::vector<ViewDesc> vd(n);
   std::vector<EdgeItem> items;
-  std::vector<RowChunk> chunks;
+  std::vector<RowChunk> chunks, rchunks;
   plan->item_begin.resize(n + 1);
   plan->chunk_begin.resize(n + 1);
+  plan->rchunk_begin.resize(n + 1);
   int64_t map_elems = 0;
   for (int v = 0; v < n; ++v) {
     const igsp_view& d = key.views[v];
@@ -247,9 +252,12 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
         items.push_back(EdgeItem{v, x0, y0, std::min(band, d.height - y0)});
     plan->chunk_begin[v] = (int)chunks.size();
     row_chunks(v, d.width, d.height, kChunkSlots, &chunks);
+    plan->rchunk_begin[v] = (int)rchunks.size();
+    row_chunks(v, d.width, d.height, kRefineChunkSlots, &rchunks);
   }
   plan->item_begin[n] = (int)items.size();
   plan->chunk_begin[n] = (int)chunks.size();
+  plan->rchunk_begin[n] = (int)rchunks.size();
   plan->map_elems = map_elems;
   // A launch over every view gives each XCD a contiguous eighth of the list
   // (the kernel's block remap); inside each eighth, full bands come first and
@@ -267,7 +275,7 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
   }
   if (upload(&plan->d_views, vd) != hipSuccess || upload(&plan->d_items, items) != hipSuccess ||
       upload(&plan->d_items_all, all) != hipSuccess ||
-      upload(&plan->d_chunks, chunks) != hipSuccess)
+      upload(&plan->d_chunks, chunks) != hipSuccess || upload(&plan->d_rchunks, rchunks) != hipSuccess)
     return IGSP_ERR_HIP;
   if (hipMalloc(&plan->d_map, (size_t)std::max<int64_t>(map_elems, 64) * esz) != hipSuccess) return IGSP_ERR_HIP;
   const size_t hb = (size_t)n * kBinsMax * sizeof(uint32_t), rb = (size_t)n * kRefineBins * sizeof(uint32_t);
@@ -450,10 +458,12 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
   auto mark = [&](int k, hipStream_t st) -> hipError_t { return ev ? hipEventRecord(ev[k], st) : hipSuccess; };
   // median selection (+ refinement passes) and normalisation of views [v0, v1)
   auto tail = [&](int v0, int v1, hipStream_t st) -> hipError_t {
-    const int f0 = P->chunk_begin[v0], f1 = P->chunk_begin[v1];
+    const int f0 = P->rchunk_begin[v0], f1 = P->rchunk_begin[v1];
+    EdgeLaunch LR = L;
+    LR.chunks = P->d_rchunks;
     hipError_t e = launch_median_select(L, v0, v1 - v0, st);
     for (int db : passes) {
-      if (e == hipSuccess) e = launch_median_refine(L, f0, f1 - f0, db, st);
+      if (e == hipSuccess) e = launch_median_refine(LR, f0, f1 - f0, db, st);
       if (e == hipSuccess) e = launch_refine_select(L, v0, v1 - v0, db, 0, st);
     }
     return e;
