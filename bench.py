@@ -588,7 +588,9 @@ def main():
 
                 def run_edge(p=p, oform=oform):
                     igsp.edge_importance(oimg, oviews, oout, precision=p, batched=oform, stream=stream)
-                ems, _ = timed(run_edge, 3, reps)
+                # warm-up long enough for the clocks to ramp up again after
+                # the host-side rendering of the workload
+                ems, _ = timed(run_edge, 50 if single else 25, reps)
                 r = {"form": f"{'plain per-view' if single else 'batched (' + oform + ')'} {p}",
                      "tile": f"{oseg}x{owgw}", "edge_ms": round(ems, 4), "mpx_per_s": round(ompx / (ems * 1e-3), 1)}
                 if not single:
