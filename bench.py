@@ -596,6 +596,13 @@ def main():
                 if not single:
                     r["algorithmic_GBps"] = round(ovb.pixels * 7 / (ems * 1e-3) / 1e9, 1)
                     r["frac_of_hbm_peak"] = round(ovb.pixels * 7 / (ems * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                if name == "views200_w1000_1560":
+                    # the same batch as one persistent launch, beside the tuned form
+                    def run_persist(p=p):
+                        igsp.edge_importance(oimg, oviews, oout, precision=p, batched="persistent", stream=stream)
+                    pms_, _ = timed(run_persist, 25, reps)
+                    r["persistent_edge_ms"] = round(pms_, 4)
+                    r["persistent_mpx_per_s"] = round(ompx / (pms_ * 1e-3), 1)
                 entry[p] = r
                 if name == "views150_2473x1643_mixed":
                     E = oout.cpu().numpy()
