@@ -702,12 +702,19 @@ __device__ __forceinline__ void load4(const EdgeLaunch& L, int64_t e, float v[4]
   }
 }
 
+// Slots' loads in flight per wavefront in the element-wise walks: 4 in their
+// own launches (lean kernels at eight waves per SIMD), 12 inside the
+// persistent kernel, whose register budget is the stencil's and whose four
+// waves per SIMD need more loads each to keep HBM busy.
+constexpr int kWalkUnroll = 4;
+constexpr int kPersistWalkUnroll = 12;
+
 // Digit histogram (into LDS) of a chunk's survivors inside the resolved
 // bucket of the radix selection, by the NW wavefronts of a work-group.
-constexpr int kRefineUnroll = 4;
 template <int PREC, int NW, bool COHERENT>
 __device__ __forceinline__ void refine_slots(const EdgeLaunch& L, const ViewDesc& vd, const RowChunk& ck,
                                              const MedState& st, int digit_bits, uint32_t* hs, int lane, int wave) {
+  constexpr int kRefineUnroll = COHERENT ? kPersistWalkUnroll : kWalkUnroll;
   const int ns = strips_of(vd);
   const int dshift = st.shift - digit_bits;
   const uint32_t dmask = (1u << digit_bits) - 1u;
@@ -788,11 +795,10 @@ __device__ __forceinline__ void normalise4(const float v[4], float med, float in
 // four values in one 16-byte store, and the last lane of a row whose width is
 // not a multiple of 4 stores its pixels one by one (a fourth value would land
 // on the next row).
-constexpr int kNormUnroll = 4;
-
 template <int PREC, int NW, bool COHERENT>
 __device__ __forceinline__ void norm_slots(const EdgeLaunch& L, const ViewDesc& vd, const RowChunk& ck, float med,
                                            int lane, int wave) {
+  constexpr int kNormUnroll = COHERENT ? kPersistWalkUnroll : kWalkUnroll;
   const int ns = strips_of(vd);
   const float inv = med > 0.0f ? 1.0f / med : 0.0f;
   // the chunk's output pixels: from its first slot's first pixel to its last
