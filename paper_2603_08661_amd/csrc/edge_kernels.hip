@@ -1254,7 +1254,18 @@ edge_persistent_kernel(EdgeLaunch L, PersistLaunch P) {
         }
       } else {
         norm_chunk<PREC, NW>(L, ck, st.med);
-        if (arrive<NW>(&sy->left[tk.phase], sy->n_chunks, &s_flag) && threadIdx.x == 0) st_agent(&sy->ready, 0u);
+        // Nothing in this launch reads the output maps, so this count-off
+        // does not wait for the task's stores: it only lets the view's last
+        // normalisation task restore the counter and reset the readiness
+        // level for the next launch, and every task that reads that level
+        // has passed its wait before it counts itself off.
+        if (threadIdx.x == 0) {
+          uint32_t* left = &sy->left[tk.phase];
+          if (__hip_atomic_fetch_add(left, 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1u) {
+            st_agent(left, sy->n_chunks);
+            st_agent(&sy->ready, 0u);
+          }
+        }
       }
     }
     __syncthreads();
