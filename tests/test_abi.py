@@ -201,3 +201,39 @@ def test_split_mask_validation():
     assert call(p=B.SelectParams(0.0, 0, -1)) == -5
     assert call(p=B.SelectParams(float("nan"), 0, 100)) == -5
     assert ctypes.sizeof(B.Contributions) == 40 and ctypes.sizeof(B.SelectParams) == 16
+
+
+def test_shipped_tuning_table_is_well_formed_and_covers_the_benchmark():
+    """Every entry of the shipped table names a form, tile and size class the
+    library accepts (batched request, staged or persistent answer, a segment
+    height of the autotuner's list, 1-8 waves), and every batched benchmark
+    geometry (in each precision it is measured in) finds an entry: the
+    table is what the benchmark's default launches read."""
+    import json
+
+    import synth
+
+    path = os.path.join(ROOT, "paper_2603_08661_amd", "tuned", "gfx950.jsonl")
+    rows = [json.loads(line) for line in open(path) if line.strip()]
+    assert rows, "empty tuning table"
+    keys = set()
+    for r in rows:
+        assert r["arch"] == "gfx950"
+        assert r["precision"] in (0, 1, 2) and r["batched"] == 1 and r["form"] in (2, 3)
+        assert r["seg_rows"] in (28, 40, 64, 88, 100, 124, 148, 196, 244) and r["wg_waves"] in (1, 2, 4, 8)
+        assert r["ms"] > 0
+        keys.add((r["precision"], r["log2_px"], r["log2_w"]))
+    assert len(keys) == len(rows), "duplicate size classes"
+
+    def ilog2(v):
+        return int(v).bit_length() - 1
+
+    prec_code = {"fp32": 0, "fp16": 1, "bf16": 2}
+    for name in ("view_256x192", "view_1297x840", "views200_w1000_1560", "views150_2473x1643_mixed",
+                 "step_views300_las3m"):
+        w = synth.workload(name)
+        widths, heights = (np.asarray(a, np.int64) for a in w.sizes())
+        key_px = ilog2(max(int((widths * heights).sum()), 1))
+        key_w = ilog2(max(int(widths.sum()) // len(widths), 1))
+        for p in w.extra.get("precisions", [w.precision]):
+            assert (prec_code[p], key_px, key_w) in keys, (name, p, key_px, key_w)
