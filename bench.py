@@ -134,8 +134,13 @@ def summarise_profile(d: str, copy_bytes: int):
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{100 * float(r['TotalDurationNs']) / total:.1f}% |")
     avg = [float(r["AverageNs"]) for r in stats if sym in r["Name"]]
+    # the dispatches one by one: the first ones run while the clocks still
+    # ramp up from idle, so the median is given beside the average
+    durs = sorted(float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+                  for r in _csv_rows(os.path.join(d, "trace", "**", "*kernel_trace.csv")) if sym in r["Kernel_Name"])
     if avg:
-        lines += ["", f"`{kernel}` average over the trace: {avg[0] / 1e6:.4f} ms; the benchmark's live "
+        med = f", median {durs[len(durs) // 2] / 1e6:.4f} ms over {len(durs)} dispatches" if durs else ""
+        lines += ["", f"`{kernel}` average over the trace: {avg[0] / 1e6:.4f} ms{med}; the benchmark's live "
                       f"measurement: {res['stage_ms']['fused']} ms."]
     open(os.path.join(ROOT, "profiles", f"{tag}_kernel_trace.md"), "w").write("\n".join(lines) + "\n")
 
