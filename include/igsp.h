@@ -175,7 +175,11 @@ igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view* views, in
  * The launch form and tile shape edge_importance would use for these views
  * and options: on return opts->batched holds the concrete igsp_form and
  * seg_rows / wg_waves are filled in (explicit values are kept; zeros become
- * the tuned entry of the size class, else the defaults 64 x 4). Tuned entries
+ * the tuned entry of the size class, else 4 wavefronts per work-group and
+ * the tallest of 64, 40, 28, 22, 16 rows that gives the stencil launch 16
+ * wavefronts per CU, or 10 rows if none does; the plain form counts the
+ * wavefronts of one view's launch, the batched forms those of all views).
+ * Tuned entries
  * come from the file IGSP_TUNE_DEFAULTS names (the shipped table, read only)
  * and then IGSP_TUNE_CACHE (the autotuner's output), read once per process.
  * opts (host, in/out). Touches no device memory and enqueues nothing.

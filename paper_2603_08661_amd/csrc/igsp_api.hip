@@ -115,8 +115,38 @@ struct EdgePlan {
 
 std::list<std::shared_ptr<EdgePlan>> g_edge_plans;  // most recently used first
 
-int default_seg_rows() { return 64; }
 int default_wg_waves() { return 4; }
+
+// Compute units of the current device (256 where none can be queried).
+int device_cus() {
+  static std::map<int, int> cache;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+  return cache[dev] = cus;
+}
+
+// Segment height when none is given or tuned: the tallest of a few heights
+// that still gives a stencil launch 16 wavefronts per CU (four per SIMD),
+// else the shortest. A wavefront's march is a chain of dependent rows, so a
+// launch with fewer wavefronts than the chip holds lasts about one segment:
+// shorter segments then save more time than their extra halo rows cost. The
+// plain form launches each view on its own, so it counts per view. (Each
+// height plus the 8 halo rows is a multiple of the loop's 6-row unroll.)
+int default_seg_rows(const igsp_view* views, int32_t n, int form) {
+  static const int kHeights[] = {64, 40, 28, 22, 16, 10};
+  const int64_t target = 16 * (int64_t)device_cus();
+  for (int seg : kHeights) {
+    int64_t waves = 0;
+    for (int i = 0; i < n; ++i)
+      waves += (int64_t)((views[i].width + kStripCols - 1) / kStripCols) * ((views[i].height + seg - 1) / seg);
+    if (form == IGSP_PLAIN && n > 0) waves /= n;
+    if (waves >= target) return seg;
+  }
+  return kHeights[sizeof(kHeights) / sizeof(kHeights[0]) - 1];
+}
 
 // ------------------------------------------------------------------ tuning
 
@@ -310,7 +340,6 @@ igsp_status ensure_persistent(EdgePlan* P) {
     return IGSP_ERR_HIP;
   const int per_cu = persistent_blocks_per_cu(prec, P->key.wg_waves);
   if (per_cu <= 0 || cus <= 0) return IGSP_ERR_HIP;
-  P->grid = per_cu * cus;
   std::vector<RowChunk> pchunks;
   std::vector<int> pchunk_begin(n + 1);
   for (int v = 0; v < n; ++v) {
@@ -318,6 +347,10 @@ igsp_status ensure_persistent(EdgePlan* P) {
     row_chunks(v, P->key.views[v].width, P->key.views[v].height, kPersistChunkSlots, &pchunks);
   }
   pchunk_begin[n] = (int)pchunks.size();
+  // resident work-groups, but no more than there are tasks (a small batch
+  // then starts and retires only the work-groups it can use)
+  const int64_t total = (int64_t)P->item_begin[n] + (int64_t)(phases - 1) * pchunk_begin[n];
+  P->grid = (int)std::min<int64_t>((int64_t)per_cu * cus, std::max<int64_t>(total, 1));
   const int64_t per_view = ((int64_t)P->item_begin[n] + (int64_t)(phases - 1) * pchunk_begin[n]) / std::max(n, 1);
   P->lag = (int)std::min<int64_t>(std::max<int64_t>(1, ((int64_t)kLagGenerations * P->grid + per_view - 1) /
                                                            std::max<int64_t>(per_view, 1)),
@@ -397,7 +430,8 @@ igsp_status get_edge_plan(const igsp_view* views, int32_t n_views, const igsp_ed
   EdgeKey key;
   key.device = dev;
   key.precision = opts ? opts->precision : IGSP_FP32;
-  int seg = default_seg_rows(), wgw = default_wg_waves();
+  const int form = resolve_form(views, n_views, opts);
+  int seg = default_seg_rows(views, n_views, form), wgw = default_wg_waves();
   if (!opts || (opts->seg_rows == 0 && opts->wg_waves == 0)) {
     load_tune_cache();
     auto it = g_tuned.find(tune_key(views, n_views, key.precision, opts ? opts->batched : IGSP_BATCHED));
@@ -409,7 +443,6 @@ igsp_status get_edge_plan(const igsp_view* views, int32_t n_views, const igsp_ed
   key.seg_rows = (opts && opts->seg_rows) ? opts->seg_rows : seg;
   key.wg_waves = (opts && opts->wg_waves) ? opts->wg_waves : wgw;
   key.views.assign(views, views + n_views);
-  const int form = resolve_form(views, n_views, opts);
   auto extras = [form](EdgePlan* P) -> igsp_status {
     if (form == IGSP_BATCHED_PERSISTENT) return ensure_persistent(P);
     if (form == IGSP_UNFUSED) return ensure_unfused(P);
@@ -812,7 +845,7 @@ extern "C" igsp_status igsp_edge_resolve(const igsp_view* views, int32_t n_views
   if (opts->batched < IGSP_PLAIN || opts->batched > IGSP_UNFUSED) return IGSP_ERR_PARAM;
   std::lock_guard<std::mutex> lk(g_mu);
   const int form = resolve_form(views, n_views, opts);
-  int seg = default_seg_rows(), wgw = default_wg_waves();
+  int seg = default_seg_rows(views, n_views, form), wgw = default_wg_waves();
   if (opts->seg_rows == 0 && opts->wg_waves == 0) {
     load_tune_cache();
     auto it = g_tuned.find(tune_key(views, n_views, opts->precision, opts->batched));
@@ -838,7 +871,7 @@ extern "C" igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view
   hipStream_t s = static_cast<hipStream_t>(stream);
   // segment heights whose rows plus the 8 halo rows are a multiple of the
   // stencil loop's 6-row unroll (no row computed past a full segment's end)
-  static const int kSeg[] = {28, 40, 64, 88, 100, 124, 148, 196, 244};
+  static const int kSeg[] = {10, 16, 22, 28, 40, 64, 88, 100, 124, 148, 196, 244};
   static const int kWaves[] = {1, 2, 4, 8};
   std::vector<int> forms;
   if (batched == IGSP_BATCHED) forms = {IGSP_BATCHED_STAGED, IGSP_BATCHED_PERSISTENT};
@@ -848,7 +881,7 @@ extern "C" igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view
     if (e0) (void)hipEventDestroy(e0);
     return IGSP_ERR_HIP;
   }
-  TuneVal bestv{default_seg_rows(), default_wg_waves(), forms.back(), 1e30};
+  TuneVal bestv{default_seg_rows(views, n_views, forms.back()), default_wg_waves(), forms.back(), 1e30};
   for (int seg : kSeg)
     for (int wgw : kWaves)
       for (int form : forms) {

@@ -174,7 +174,9 @@ def test_tuning_table_lookup_and_override(tmp_path):
     env = dict(os.environ, IGSP_TUNE_DEFAULTS=str(table), IGSP_TUNE_CACHE=str(cache))
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
                          check=True).stdout.strip()
-    assert out == ("('persistent', 96, 2) ('staged', 64, 4) ('persistent', 32, 4) ('staged', 64, 4)"), out
+    # no entry: 4 wavefronts per work-group and, for one 1000 x 800 view (5 strips), the shortest
+    # segment height, since no height gives the stencil launch 16 wavefronts per CU
+    assert out == ("('persistent', 96, 2) ('staged', 10, 4) ('persistent', 32, 4) ('staged', 10, 4)"), out
     cache.write_text(row.format(s=48, w=8, f=2) + "\n")
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
                          check=True).stdout.strip()
@@ -220,7 +222,7 @@ def test_shipped_tuning_table_is_well_formed_and_covers_the_benchmark():
     for r in rows:
         assert r["arch"] == "gfx950"
         assert r["precision"] in (0, 1, 2) and r["batched"] == 1 and r["form"] in (2, 3)
-        assert r["seg_rows"] in (28, 40, 64, 88, 100, 124, 148, 196, 244) and r["wg_waves"] in (1, 2, 4, 8)
+        assert r["seg_rows"] in (10, 16, 22, 28, 40, 64, 88, 100, 124, 148, 196, 244) and r["wg_waves"] in (1, 2, 4, 8)
         assert r["ms"] > 0
         keys.add((r["precision"], r["log2_px"], r["log2_w"]))
     assert len(keys) == len(rows), "duplicate size classes"
@@ -237,3 +239,25 @@ def test_shipped_tuning_table_is_well_formed_and_covers_the_benchmark():
         key_w = ilog2(max(int(widths.sum()) // len(widths), 1))
         for p in w.extra.get("precisions", [w.precision]):
             assert (prec_code[p], key_px, key_w) in keys, (name, p, key_px, key_w)
+
+
+def test_default_segment_height_follows_the_launch_size():
+    """With no tuned entry, the segment height is the tallest of 64, 40, 28,
+    22, 16 rows that gives the stencil launch 16 wavefronts per CU (no device
+    here: 256 CUs, 4096 wavefronts), else 10; the plain form counts one
+    view's launch, the batched forms all views together."""
+    import subprocess
+    import sys
+
+    code = ("import paper_2603_08661_amd as g\n"
+            "def v(n, w, h): return ([w] * n, [h] * n, [0] * n, [0] * n)\n"
+            "print([g.edge_resolve(v(*a), 'bf16', f)[1] for a, f in ("
+            "((300, 2000, 1300), 'staged'), ((60, 1000, 800), 'staged'), ((40, 1000, 800), 'staged'),"
+            "((300, 2000, 1300), 'plain'), ((1, 3840, 2160), 'plain'), ((1, 256, 192), 'staged'))])\n")
+    env = dict(os.environ, IGSP_TUNE_DEFAULTS="", IGSP_TUNE_CACHE="")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         check=True).stdout.strip()
+    # 300 x 9 strips x 21 segments of 64 rows = 56700; 60 x 5 x 13 = 3900 < 4096 <= 60 x 5 x 20 = 6000;
+    # 40 x 5 x 20 = 4000, 40 x 5 x 29 = 5800 (28 rows); one 2000 x 1300 view: 9 x 130 = 1170 at 10 rows;
+    # 3840 x 2160: 16 x 216 = 3456 at 10 rows
+    assert out == "[64, 40, 28, 10, 10, 10]", out
