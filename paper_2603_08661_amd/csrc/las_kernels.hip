@@ -2,7 +2,9 @@
 // the column-extraction transform of Algorithm 2).
 //
 // Three launches, so the split is all-or-nothing and the live count N can
-// stay on the device (a captured graph stays valid as N grows):
+// stay on the device (a captured graph stays valid as N grows); a small plain
+// split (capacity <= 65536 rows) runs the same steps in one work-group and
+// one launch (las_small_kernel):
 //   las_count : per tile of 2048 live rows, the number of selected rows
 //               (8 mask bytes per lane, a byte-wise non-zero test, popcount);
 //   las_scan  : one work-group: exclusive scan of the live tiles' counts, K,
@@ -385,9 +387,69 @@ __global__ __launch_bounds__(kLasThreads) __attribute__((amdgpu_waves_per_eu(4))
   split_tiles<true>(L);
 }
 
+// A small plain split (capacity <= kLasSmallCapacity rows) in one launch by
+// one work-group: it counts the selected rows, takes the capacity decision,
+// then compacts and splits them round by round (8 rows per thread and
+// round). Same rows, same order, same all-or-nothing rule as the three
+// launches; a call then costs one launch instead of three.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallRows = 8 * kSmallThreads;
+constexpr int64_t kLasSmallCapacity = 8 * kSmallRows;
+
+__global__ __launch_bounds__(kSmallThreads) void las_small_kernel(LasLaunch L) {
+  __shared__ int32_t rows[kSmallRows];
+  __shared__ int wsum[kSmallThreads / 64];
+  __shared__ int s_ok;
+  const int64_t N = live_rows(L);
+  const int rounds = (int)((N + kSmallRows - 1) / kSmallRows);
+  int64_t K = 0;  // the same in every thread (a work-group total)
+  for (int r = 0; r < rounds; ++r) {
+    int total = 0;
+    (void)wg_scan<kSmallThreads>(__popcll(nonzero_bytes(mask8(L, (int64_t)r * kSmallRows + 8 * threadIdx.x, N))),
+                                 wsum, total);
+    K += total;
+  }
+  if (threadIdx.x == 0) {
+    const int64_t n_raw = *L.g.count;
+    const bool valid = n_raw >= 0 && n_raw <= L.g.capacity;
+    const bool ok = valid && n_raw + K <= L.g.capacity;
+    L.scalars->n_live = n_raw;
+    L.scalars->k = K;
+    L.scalars->ok = ok ? 1 : 0;
+    *L.status = ok ? IGSP_OK : IGSP_ERR_CAPACITY;
+    if (L.n_split) *L.n_split = K;
+    if (ok) *L.g.count = n_raw + K;
+    s_ok = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_ok) return;  // uniform
+  int64_t first = 0;
+  for (int r = 0; r < rounds; ++r) {
+    const int64_t base = (int64_t)r * kSmallRows;
+    const uint64_t nz = nonzero_bytes(mask8(L, base + 8 * threadIdx.x, N));
+    int total = 0;
+    int pos = wg_scan<kSmallThreads>(__popcll(nz), wsum, total);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if ((nz >> (8 * k)) & 1ull) rows[pos++] = 8 * threadIdx.x + k;
+    __syncthreads();
+    for (int k = threadIdx.x; k < total; k += kSmallThreads) split_row(L, base + rows[k], N + first + k, first + k);
+    first += total;
+    __syncthreads();  // rows[] is rewritten by the next round
+  }
+}
+
 }  // namespace
 
 hipError_t launch_las(const LasLaunch& L, hipStream_t s) {
+  const igsp_adam_moments& A = L.adam;
+  bool full = L.g.feat_dim > 0;
+  for (int m = 0; m < 2; ++m)
+    full = full || A.means[m] || A.log_scales[m] || A.quats[m] || A.opacity_logits[m] || A.features[m];
+  if (!full && L.g.capacity <= kLasSmallCapacity) {
+    hipLaunchKernelGGL(las_small_kernel, dim3(1), dim3(kSmallThreads), 0, s, L);
+    return hipGetLastError();
+  }
   // grids are fixed by the capacity (the live count is only known on the
   // device); work-groups stride over the live tiles
   const int grid = L.n_blocks < kLasGrid ? L.n_blocks : kLasGrid;
@@ -397,10 +459,6 @@ hipError_t launch_las(const LasLaunch& L, hipStream_t s) {
   hipLaunchKernelGGL(las_scan_kernel, dim3(1), dim3(1024), 0, s, L);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const igsp_adam_moments& A = L.adam;
-  bool full = L.g.feat_dim > 0;
-  for (int m = 0; m < 2; ++m)
-    full = full || A.means[m] || A.log_scales[m] || A.quats[m] || A.opacity_logits[m] || A.features[m];
   if (full) hipLaunchKernelGGL(las_split_full_kernel, dim3(grid), dim3(kLasThreads), 0, s, L);
   else hipLaunchKernelGGL(las_split_kernel, dim3(grid), dim3(kLasThreads), 0, s, L);
   return hipGetLastError();

@@ -111,8 +111,12 @@ def test_workloads(name):
 
 
 @pytest.mark.parametrize("N,frac,extra", [(0, 0.0, 5), (1, 1.0, 0), (2047, 1.0, 0), (2048, 0.5, 1),
-                                          (2049, 0.0, 10), (5000, 0.3, 3), (70001, 0.01, 0)])
+                                          (2049, 0.0, 10), (5000, 0.3, 3), (8193, 0.5, 0), (60000, 0.05, 0),
+                                          (64000, 0.024, 0), (64000, 0.024, 1), (70001, 0.01, 0)])
 def test_sizes_and_densities(N, frac, extra):
+    """Capacities up to 65536 rows take the one-launch split of one
+    work-group (rounds of 8192 rows), larger ones the three launches; 64000
+    rows with 1536 selected sit on either side of that line."""
     g = synth.gaussians(17, max(N, 1))
     K = int(round(frac * N))
     mk = synth.mask(18, max(N, 1), K)[:N]
