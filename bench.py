@@ -89,7 +89,7 @@ def _counter_kib(rows, name_part: str, counter: str):
 def kernel_part(name: str) -> str:
     """The part of the hot path a traced kernel belongs to."""
     parts = (("edge_fused", "edge: fused stencil"), ("edge_persistent", "edge: persistent form"),
-             ("median_", "edge: median"), ("refine_select", "edge: median"), ("normalise", "edge: normalise"),
+             ("median_", "edge: median"), ("normalise", "edge: normalise"),
              ("uf_", "edge: unfused ablation"), ("las_", "Long-Axis-Split (and full record)"),
              ("sel_", "split mask"), ("copyBuffer", "runtime copy"), ("Fill", "torch fill"))
     for key, part in parts:

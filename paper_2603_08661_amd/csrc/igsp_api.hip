@@ -308,15 +308,18 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
       upload(&plan->d_chunks, chunks) != hipSuccess || upload(&plan->d_rchunks, rchunks) != hipSuccess)
     return IGSP_ERR_HIP;
   if (hipMalloc(&plan->d_map, (size_t)std::max<int64_t>(map_elems, 64) * esz) != hipSuccess) return IGSP_ERR_HIP;
-  const size_t hb = (size_t)n * kBinsMax * sizeof(uint32_t), rb = (size_t)n * kRefineBins * sizeof(uint32_t);
+  // refinement histograms of up to two passes, selection states after 0, 1
+  // and 2 refinement steps
+  const size_t hb = (size_t)n * kBinsMax * sizeof(uint32_t), rb = (size_t)2 * n * kRefineBins * sizeof(uint32_t),
+               sb = (size_t)3 * n * sizeof(MedState);
   if (hipMalloc(reinterpret_cast<void**>(&plan->d_hist), hb) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&plan->d_rhist), rb) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&plan->d_state), (size_t)n * sizeof(MedState)) != hipSuccess)
+      hipMalloc(reinterpret_cast<void**>(&plan->d_state), sb) != hipSuccess)
     return IGSP_ERR_HIP;
   // Histograms start at zero once; every call's selection kernels clear them
   // again after reading, so later calls need no memset (capturable).
   if (hipMemset(plan->d_hist, 0, hb) != hipSuccess || hipMemset(plan->d_rhist, 0, rb) != hipSuccess ||
-      hipMemset(plan->d_state, 0, (size_t)n * sizeof(MedState)) != hipSuccess ||
+      hipMemset(plan->d_state, 0, sb) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess)
     return IGSP_ERR_HIP;
   g_edge_plans.push_front(std::move(plan));
@@ -473,6 +476,7 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
   L.hist = P->d_hist;
   L.rhist = P->d_rhist;
   L.state = P->d_state;
+  L.n_views = P->n_views;
   L.medians_dn = opts ? opts->medians : nullptr;
   L.survivors = opts ? opts->survivors : nullptr;
   L.stage_events = opts ? reinterpret_cast<hipEvent_t*>(opts->stage_events) : nullptr;
@@ -483,10 +487,9 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
   const int form = resolve_form(P->key.views.data(), P->n_views, opts);
   const bool batched = form != IGSP_PLAIN;
   const int n = P->n_views;
-  // refinement passes of the median's radix selection: (digit bits) per pass
-  std::vector<int> passes;
-  if (L.precision == IGSP_FP16) passes = {3};
-  else if (L.precision == IGSP_FP32) passes = {8, 8};
+  // refinement passes of the median's radix selection (3-bit digits for
+  // FP16, 8-bit for FP32; BF16 is resolved by the first histogram)
+  const int passes = L.precision == IGSP_FP16 ? 1 : (L.precision == IGSP_FP32 ? 2 : 0);
   hipEvent_t* ev = L.stage_events;
   auto mark = [&](int k, hipStream_t st) -> hipError_t { return ev ? hipEventRecord(ev[k], st) : hipSuccess; };
   // median selection (+ refinement passes) and normalisation of views [v0, v1)
@@ -495,10 +498,10 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
     EdgeLaunch LR = L;
     LR.chunks = P->d_rchunks;
     hipError_t e = launch_median_select(L, v0, v1 - v0, st);
-    for (int db : passes) {
-      if (e == hipSuccess) e = launch_median_refine(LR, f0, f1 - f0, db, st);
-      if (e == hipSuccess) e = launch_refine_select(L, v0, v1 - v0, db, 0, st);
-    }
+    // each refinement pass takes the previous pass's selection step itself;
+    // the last one is taken by a launch of its own or by the normalisation
+    for (int p = 0; p < passes && e == hipSuccess; ++p) e = launch_median_refine(LR, f0, f1 - f0, p, st);
+    if (e == hipSuccess) e = launch_median_step(L, v0, v1 - v0, st);
     return e;
   };
   auto stencil = [&](int v0, int v1, hipStream_t st) -> hipError_t {
@@ -520,7 +523,7 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
     PL.sync = P->d_sync;
     PL.ctl = P->d_ctl;
     PL.n_tasks = P->n_tasks;
-    PL.levels = (int)passes.size();
+    PL.levels = passes;
     PL.n_views = P->n_views;
     PL.spin_limit = kSpinLimit;
     PL.wait_bias = 0;

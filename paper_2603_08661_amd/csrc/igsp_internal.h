@@ -93,8 +93,8 @@ struct EdgeLaunch {
   const RowChunk* chunks;
   void* map;
   uint32_t* hist;            // [n_views][kBinsMax]
-  uint32_t* rhist;           // [n_views][kRefineBins]
-  MedState* state;           // [n_views]
+  uint32_t* rhist;           // [2][n_views][kRefineBins]: refinement pass p's digit histograms
+  MedState* state;           // [3][n_views]: the selection state after p refinement steps
   float* medians_dn;         // optional outputs
   int32_t* survivors;
   hipEvent_t* stage_events;  // optional, 4 events
@@ -102,6 +102,7 @@ struct EdgeLaunch {
   int precision;
   int wg_waves;
   int seg_rows;
+  int n_views;               // views of the plan (the stride of state and rhist)
 };
 
 // Work list of the single persistent launch of the batched form. Phases of
@@ -171,9 +172,9 @@ struct UfLaunch {
 // tables; view ranges are [v0, v1)).
 hipError_t launch_edge_fused(const EdgeLaunch& L, int item0, int n_items, hipStream_t s);
 hipError_t launch_median_select(const EdgeLaunch& L, int v0, int nv, hipStream_t s);
-hipError_t launch_median_refine(const EdgeLaunch& L, int chunk0, int n_chunks, int digit_bits, hipStream_t s);
-hipError_t launch_refine_select(const EdgeLaunch& L, int v0, int nv, int digit_bits, int final_shift,
-                                hipStream_t s);
+hipError_t launch_median_refine(const EdgeLaunch& L, int chunk0, int n_chunks, int pass, hipStream_t s);
+// the last selection step where the normalisation does not take it (no-op otherwise)
+hipError_t launch_median_step(const EdgeLaunch& L, int v0, int nv, hipStream_t s);
 hipError_t launch_normalise(const EdgeLaunch& L, int chunk0, int n_chunks, hipStream_t s);
 // The stencil steps of the unfused form: gray, blur, Sobel, suppression
 // (+ histogram), four launches; the median and normalisation follow as in the
