@@ -119,7 +119,9 @@ int default_wg_waves() { return 4; }
 
 // Compute units of the current device (256 where none can be queried).
 int device_cus() {
+  static std::mutex mu;
   static std::map<int, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
   auto it = cache.find(dev);
@@ -176,7 +178,9 @@ int ilog2(int64_t v) {
 
 // Architecture name of the current device ("gfx950"), cached per device.
 std::string device_arch() {
+  static std::mutex mu;
   static std::map<int, std::string> cache;
+  std::lock_guard<std::mutex> lk(mu);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return "unknown";
   auto it = cache.find(dev);
