@@ -920,9 +920,9 @@ extern "C" igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view
   // candidate untimed a while before any timing
   float ms = 0.0f;
   for (int k = 0; k < 4 && st == IGSP_OK; ++k) st = time_candidate(cands.front(), 4, &ms);
-  // round 1: every candidate once; round 2: the three fastest again, three
-  // times each in turn, each keeping its best (the choice between close
-  // candidates then rests on more than one sample)
+  // round 1: every candidate once; round 2: the three fastest again, five
+  // times each in turn over twice the launches, each keeping its best (the
+  // choice between close candidates then rests on more than one sample)
   for (auto& c : cands) {
     if (st != IGSP_OK) break;
     st = time_candidate(c, 8, &ms);
@@ -930,9 +930,9 @@ extern "C" igsp_status igsp_edge_autotune(const uint8_t* images, const igsp_view
   }
   std::sort(cands.begin(), cands.end(), [](const TuneVal& x, const TuneVal& y) { return x.ms < y.ms; });
   const size_t top = std::min<size_t>(3, cands.size());
-  for (int round = 0; round < 3 && st == IGSP_OK; ++round)
+  for (int round = 0; round < 5 && st == IGSP_OK; ++round)
     for (size_t k = 0; k < top && st == IGSP_OK; ++k) {
-      st = time_candidate(cands[k], 8, &ms);
+      st = time_candidate(cands[k], 16, &ms);
       cands[k].ms = std::min<double>(cands[k].ms, ms);
     }
   TuneVal bestv{default_seg_rows(views, n_views, forms.back()), default_wg_waves(), forms.back(), 1e30};
