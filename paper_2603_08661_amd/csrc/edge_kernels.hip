@@ -297,9 +297,6 @@ struct StripCtx {
   uint8_t* map;                    // this strip's rows of the stored map
 };
 
-// Offset past any map row: buffer accesses beyond a descriptor's size are
-// dropped by the hardware, so every lane can issue the same stores.
-constexpr int kDropOffset = 0x40000000;
 
 // Cache policy of buffer accesses: 0 = default; kCpolAgent = device-coherent
 // (the SC1 scope bit, the same encoding the compiler gives agent-scope
@@ -651,9 +648,11 @@ __global__ __launch_bounds__(256) void median_select_kernel(EdgeLaunch L, int v0
   }
 #pragma unroll
   for (int j = 0; j < PER; ++j) h[b0 + j] = 0;  // ready for the next call
-  // the digit histograms of this view's refinement passes start from zero
+  // the digit histograms of this view's refinement passes and its
+  // candidate count start from zero
   for (int p = 0; p < refine_passes(PREC); ++p)
     L.rhist[((int64_t)p * L.n_views + v) * kRefineBins + threadIdx.x] = 0;
+  if (L.cand_n && threadIdx.x == 0) L.cand_n[v] = 0;
 }
 
 // One refinement step of view v's radix selection, taken by a 256-thread
@@ -753,9 +752,15 @@ constexpr int kPersistWalkUnroll = 12;
 
 // Digit histogram (into LDS) of a chunk's survivors inside the resolved
 // bucket of the radix selection, by the NW wavefronts of a work-group.
-template <int PREC, int NW, bool COHERENT>
+// APPEND also gathers each of them in the work-group's LDS list lds_cand
+// (count in *lds_n; the first FP32 pass: the second then reads the view's
+// list instead of the map).
+constexpr int kLdsCand = 2048;  // candidates a work-group gathers before it flushes them
+
+template <int PREC, int NW, bool COHERENT, bool APPEND = false>
 __device__ __forceinline__ void refine_slots(const EdgeLaunch& L, const ViewDesc& vd, const RowChunk& ck,
-                                             const MedState& st, int digit_bits, uint32_t* hs, int lane, int wave) {
+                                             const MedState& st, int digit_bits, uint32_t* hs, int lane, int wave,
+                                             uint32_t* lds_cand = nullptr, uint32_t* lds_n = nullptr) {
   constexpr int kRefineUnroll = COHERENT ? kPersistWalkUnroll : kWalkUnroll;
   const int ns = strips_of(vd);
   const int dshift = st.shift - digit_bits;
@@ -770,15 +775,30 @@ __device__ __forceinline__ void refine_slots(const EdgeLaunch& L, const ViewDesc
       a[k] = view_slot(vd, ns, min(u0 + k * NW, ck.u1 - 1), lane);
       load4<PREC, COHERENT>(L, a[k].stored, v[k]);
     }
+    uint32_t hit = 0;  // bit 4k + i: value i of slot k is counted
 #pragma unroll
     for (int k = 0; k < kRefineUnroll; ++k) {
       if (u0 + k * NW >= ck.u1) break;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const uint32_t bits = __float_as_uint(v[k][i]);
-        if (i < a[k].valid && v[k][i] > 0.0f && (bits >> st.shift) == st.prefix)
+        if (i < a[k].valid && v[k][i] > 0.0f && (bits >> st.shift) == st.prefix) {
           atomicAdd(&hs[(bits >> dshift) & dmask], 1u);
+          hit |= 1u << (4 * k + i);
+        }
       }
+    }
+    if constexpr (APPEND) {
+      // the counted values go to the work-group's LDS list (flushed to the
+      // view's list once per work-group by the caller)
+#pragma unroll
+      for (int k = 0; k < kRefineUnroll; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if ((hit >> (4 * k + i)) & 1u) {
+            const uint32_t at = atomicAdd(lds_n, 1u);
+            if (at < (uint32_t)kLdsCand) lds_cand[at] = __float_as_uint(v[k][i]);
+          }
     }
   }
 }
@@ -805,8 +825,41 @@ __global__ __launch_bounds__(256) void median_refine_kernel(EdgeLaunch L, int ch
   const ViewDesc vd = L.views[v];
   hs[threadIdx.x] = 0;
   __syncthreads();
-  if (st.n > 0 && st.shift > final_shift(PREC))
-    refine_slots<PREC, 4, false>(L, vd, ck, st, DB, hs, __lane_id(), __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+  const int lane = __lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (st.n > 0 && st.shift > final_shift(PREC)) {
+    if (PREC == IGSP_FP32 && pass == 0 && L.use_cand && vd.cand_cap > 0) {
+      __shared__ uint32_t cand[kLdsCand];
+      __shared__ uint32_t cn, cbase;
+      if (threadIdx.x == 0) cn = 0;
+      __syncthreads();
+      refine_slots<PREC, 4, false, true>(L, vd, ck, st, DB, hs, lane, wave, cand, &cn);
+      __syncthreads();
+      // one reservation per work-group; a work-group that found more than
+      // its LDS list holds marks the view's list as overflowed instead
+      if (threadIdx.x == 0)
+        cbase = atomicAdd(&L.cand_n[v], cn <= (uint32_t)kLdsCand ? cn : (uint32_t)vd.cand_cap + 1u);
+      __syncthreads();
+      if (cn <= (uint32_t)kLdsCand)
+        for (uint32_t k = threadIdx.x; k < cn; k += 256)
+          if (cbase + k < (uint32_t)vd.cand_cap) L.cand[vd.cand_off + cbase + k] = cand[k];
+    } else if (PREC == IGSP_FP32 && pass == 1 && L.use_cand && vd.cand_cap > 0 &&
+               L.cand_n[v] <= (uint32_t)vd.cand_cap) {
+      // the second FP32 pass counts the first pass's candidates, not the
+      // map: every survivor of the new bucket is one of them. The view's
+      // chunks share the list evenly, in chunk order.
+      const uint32_t nc = L.cand_n[v];
+      const uint32_t chunks = (uint32_t)((strips_of(vd) * (int64_t)vd.H + kRefineChunkSlots - 1) / kRefineChunkSlots);
+      const uint32_t j = (uint32_t)(ck.u0 / kRefineChunkSlots), per = (nc + chunks - 1) / chunks;
+      const uint32_t c0 = min(nc, j * per), c1 = min(nc, c0 + per);
+      const int dshift = st.shift - DB;
+      for (uint32_t k = c0 + threadIdx.x; k < c1; k += 256) {
+        const uint32_t bits = L.cand[vd.cand_off + k];
+        if ((bits >> st.shift) == st.prefix) atomicAdd(&hs[(bits >> dshift) & ((1u << DB) - 1u)], 1u);
+      }
+    } else {
+      refine_slots<PREC, 4, false>(L, vd, ck, st, DB, hs, lane, wave);
+    }
+  }
   __syncthreads();
   const uint32_t c = hs[threadIdx.x];
   if (c) atomicAdd(&L.rhist[(pass * n + v) * kRefineBins + threadIdx.x], c);

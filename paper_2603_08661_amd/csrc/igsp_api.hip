@@ -25,7 +25,6 @@ namespace {
 // median's refinement passes (coarser: each work-group clears and flushes a
 // histogram) and per element-wise task of the persistent form.
 constexpr int kChunkSlots = 16;
-constexpr int kRefineChunkSlots = 64;
 constexpr int kPersistChunkSlots = 264;
 // Distance, in tasks, between a view's phases in the persistent task list, as
 // a multiple of the resident work-groups: a task handed out that many
@@ -88,6 +87,8 @@ struct EdgePlan {
   EdgeItem* d_items_all = nullptr;  // the same items in the order of a launch over every view
   RowChunk* d_chunks = nullptr;
   RowChunk* d_rchunks = nullptr;  // the refinement passes' coarser chunks
+  uint32_t* d_cand = nullptr;     // FP32: median candidates and their counts per view
+  uint32_t* d_cand_n = nullptr;
   std::vector<int> item_begin, chunk_begin, rchunk_begin;  // per view, size n_views + 1
   void* d_map = nullptr;
   uint32_t* d_hist = nullptr;
@@ -105,7 +106,7 @@ struct EdgePlan {
   int64_t map_elems = 0;
   ~EdgePlan() {
     (void)hipFree(d_views); (void)hipFree(d_items); (void)hipFree(d_items_all); (void)hipFree(d_chunks);
-    (void)hipFree(d_rchunks); (void)hipFree(d_map);
+    (void)hipFree(d_rchunks); (void)hipFree(d_cand); (void)hipFree(d_cand_n); (void)hipFree(d_map);
     (void)hipFree(d_hist); (void)hipFree(d_rhist); (void)hipFree(d_state);
     (void)hipFree(d_pchunks); (void)hipFree(d_tasks); (void)hipFree(d_sync); (void)hipFree(d_ctl);
     (void)hipFree(const_cast<UfItem*>(uf.items)); (void)hipFree(uf.gray); (void)hipFree(uf.blur);
@@ -272,13 +273,21 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
   plan->item_begin.resize(n + 1);
   plan->chunk_begin.resize(n + 1);
   plan->rchunk_begin.resize(n + 1);
-  int64_t map_elems = 0;
+  int64_t map_elems = 0, cand_elems = 0;
   for (int v = 0; v < n; ++v) {
     const igsp_view& d = key.views[v];
     // the stored map, strip by strip (each strip's rows one after another,
     // in slots of 256 values)
     const int strips = (d.width + kStripCols - 1) / kStripCols;
-    vd[v] = ViewDesc{d.width, d.height, d.in_offset, d.out_offset, map_elems, d.height, 0};
+    vd[v] = ViewDesc{d.width, d.height, d.in_offset, d.out_offset, map_elems, d.height, 0, cand_elems};
+    if (key.precision == IGSP_FP32) {
+      // room for 1/16 of the view's pixels: the first histogram's median
+      // bucket (1/128 of a binade) holds far fewer survivors unless the
+      // view's magnitudes are nearly all equal, and then the list is not used
+      const int64_t px = (int64_t)d.width * d.height;
+      vd[v].cand_cap = (int32_t)std::min<int64_t>(std::max<int64_t>(px / 16, 256), INT32_MAX);
+      cand_elems += vd[v].cand_cap;
+    }
     map_elems += (int64_t)strips * d.height * kSlotPitch;
     plan->item_begin[v] = (int)items.size();
     for (int x0 = 0; x0 < d.width; x0 += kStripCols)
@@ -312,6 +321,10 @@ igsp_status build_edge_plan(const EdgeKey& key, std::shared_ptr<EdgePlan>* out) 
       upload(&plan->d_chunks, chunks) != hipSuccess || upload(&plan->d_rchunks, rchunks) != hipSuccess)
     return IGSP_ERR_HIP;
   if (hipMalloc(&plan->d_map, (size_t)std::max<int64_t>(map_elems, 64) * esz) != hipSuccess) return IGSP_ERR_HIP;
+  if (cand_elems > 0 &&
+      (hipMalloc(reinterpret_cast<void**>(&plan->d_cand), (size_t)cand_elems * sizeof(uint32_t)) != hipSuccess ||
+       hipMalloc(reinterpret_cast<void**>(&plan->d_cand_n), (size_t)n * sizeof(uint32_t)) != hipSuccess))
+    return IGSP_ERR_HIP;
   // refinement histograms of up to two passes, selection states after 0, 1
   // and 2 refinement steps
   const size_t hb = (size_t)n * kBinsMax * sizeof(uint32_t), rb = (size_t)2 * n * kRefineBins * sizeof(uint32_t),
@@ -480,6 +493,9 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
   L.hist = P->d_hist;
   L.rhist = P->d_rhist;
   L.state = P->d_state;
+  L.cand = P->d_cand;
+  L.cand_n = P->d_cand_n;
+  L.use_cand = 0;
   L.n_views = P->n_views;
   L.medians_dn = opts ? opts->medians : nullptr;
   L.survivors = opts ? opts->survivors : nullptr;
@@ -501,6 +517,10 @@ igsp_status enqueue_edge(EdgePlan* P, const uint8_t* images, int64_t img_end, fl
     const int f0 = P->rchunk_begin[v0], f1 = P->rchunk_begin[v1];
     EdgeLaunch LR = L;
     LR.chunks = P->d_rchunks;
+    // FP32 candidate lists where a launch covers several views (one view's
+    // launches are bound by latency, and the list's extra steps cost more
+    // than the second pass's bytes: +2% for the plain form, measured)
+    LR.use_cand = L.cand && v1 - v0 > 1;
     hipError_t e = launch_median_select(L, v0, v1 - v0, st);
     // each refinement pass takes the previous pass's selection step itself;
     // the last one is taken by a launch of its own or by the normalisation

@@ -38,6 +38,7 @@ constexpr uint32_t kKeyLoSquare = 127u * 128u;             // float32 exponent o
 constexpr int kBinsSquare = 58 * 128;                      // 1 .. 2^58
 constexpr int kBinsMax = kBinsSquare;
 constexpr int kRefineBins = 256;          // radix digit of the refine passes
+constexpr int kRefineChunkSlots = 64;     // slots per work-group of a refinement pass
 
 // The stored intermediate of a view is kept strip by strip: strip s (output
 // columns 248 s .. 248 s + 247) holds its rows one after another in slots of
@@ -55,7 +56,8 @@ struct ViewDesc {
   int64_t out_off;     // floats from `out_maps`
   int64_t map_off;     // elements from the plan's map buffer
   int32_t strip_rows;  // rows per strip of the stored map (H)
-  int32_t pad;
+  int32_t cand_cap;    // FP32: room for the view's median candidates (0: none)
+  int64_t cand_off;    // first candidate of the view in the candidate buffer
 };
 
 struct EdgeItem {    // one work-group of the fused stencil kernel
@@ -95,6 +97,9 @@ struct EdgeLaunch {
   uint32_t* hist;            // [n_views][kBinsMax]
   uint32_t* rhist;           // [2][n_views][kRefineBins]: refinement pass p's digit histograms
   MedState* state;           // [3][n_views]: the selection state after p refinement steps
+  uint32_t* cand;            // FP32: survivors in the first histogram's median bucket, per view
+  uint32_t* cand_n;          // [n_views]: candidates found (more than the room: list not used)
+  int use_cand;              // the refinement passes of this launch use the candidate lists
   float* medians_dn;         // optional outputs
   int32_t* survivors;
   hipEvent_t* stage_events;  // optional, 4 events

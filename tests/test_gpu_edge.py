@@ -201,3 +201,29 @@ def test_more_geometries_than_the_plan_cache_holds():
         for k in (list(range(10)) if rnd == 0 else list(range(9, -1, -2)) + list(range(0, 10, 2))):
             E, med, nsv = gpu_edge(batches[k], "bf16", "staged")
             compare_view(view_map(E, batches[k], 0), refs[k], "bf16", med[0], nsv[0])
+
+
+@pytest.mark.parametrize("form", ["plain", "staged", "unfused"])
+def test_fp32_median_candidates_overflow_and_fit(form):
+    """In launches over several views (staged, unfused), the second FP32
+    refinement pass reads the first pass's candidate list (the survivors of
+    the first histogram's median bucket) when it fits in the view's room
+    (1/16 of its pixels, at least 256), else the map; the plain form's
+    one-view launches always read the map. A striped view puts nearly every
+    survivor in one bucket (the list overflows); a textured view of the same
+    size does not. Every view matches the oracle."""
+    H, W = 64, 600
+    stripes = np.zeros((H, W, 3), np.uint8)
+    stripes[:] = ((((np.arange(W) // 3) % 2) * 180) + 30).astype(np.uint8)[None, :, None]
+    textured = synth.image(77, W, H, n_poly=8, texture=True)
+    room = max(H * W // 16, 256)
+    counts = []
+    for im in (stripes, textured):
+        o = oracle.edge_view(im)
+        keep = o["keep"].astype(bool)
+        bits = o["M"][keep].astype(np.float32).view(np.uint32)
+        med = np.float32(o["Mmed"]).view(np.uint32)
+        counts.append(int(((bits >> 16) == (med >> 16)).sum()))
+    assert counts[0] > room >= counts[1], (counts, room)
+    vb = synth.pack_views([stripes, textured, stripes], in_align=3, out_align=2)
+    check_batch(vb, "fp32", form)
