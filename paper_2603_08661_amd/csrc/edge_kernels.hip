@@ -835,9 +835,12 @@ __global__ __launch_bounds__(256) void median_refine_kernel(EdgeLaunch L, int ch
       refine_slots<PREC, 4, false, true>(L, vd, ck, st, DB, hs, lane, wave, cand, &cn);
       __syncthreads();
       // one reservation per work-group; a work-group that found more than
-      // its LDS list holds marks the view's list as overflowed instead
-      if (threadIdx.x == 0)
-        cbase = atomicAdd(&L.cand_n[v], cn <= (uint32_t)kLdsCand ? cn : (uint32_t)vd.cand_cap + 1u);
+      // its LDS list holds marks the view's list as overflowed instead (bit
+      // 31: the counts themselves stay below 2^31, a view's pixel count)
+      if (threadIdx.x == 0) {
+        if (cn <= (uint32_t)kLdsCand) cbase = atomicAdd(&L.cand_n[v], cn);
+        else atomicOr(&L.cand_n[v], 0x80000000u);
+      }
       __syncthreads();
       if (cn <= (uint32_t)kLdsCand)
         for (uint32_t k = threadIdx.x; k < cn; k += 256)
