@@ -53,7 +53,7 @@ def _las_result(gt, sidx, status, nsplit, host, mk):
 
 
 @pytest.mark.parametrize("precision,form", [("bf16", "persistent"), ("fp32", "persistent"), ("bf16", "staged"),
-                                            ("fp16", "persistent"), ("fp16", "staged")])
+                                            ("fp16", "persistent"), ("fp16", "staged"), ("fp32", "staged")])
 def test_graph_replays_match_oracle_and_eager(precision, form):
     import torch
 
