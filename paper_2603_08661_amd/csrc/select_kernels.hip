@@ -67,9 +67,15 @@ constexpr int kScatterSlots = 1024;  // 12 KB of LDS: keys and 64-bit sums
 constexpr int kScatterProbes = 16;
 static_assert(kScatterSlots == 1 << 10, "the slot hash keeps the top 10 bits");
 
+// LDS_VIEWS: the view table is copied into (dynamic) LDS first, so each
+// contribution's map read waits on one global load fewer.
+constexpr int kSelLdsViews = 512;  // at most this many views go to LDS (8 KB)
+
+template <bool LDS_VIEWS>
 __global__ __launch_bounds__(kSelThreads) void sel_scatter_kernel(SelLaunch S) {
   __shared__ int32_t keys[kScatterSlots];
   __shared__ unsigned long long sums[kScatterSlots];
+  extern __shared__ SelView lviews[];
   constexpr int64_t kChunk = (int64_t)kScatterRounds * kSelThreads;
   const int64_t N = live_count(S);
   const int lane = threadIdx.x & 63;
@@ -77,24 +83,44 @@ __global__ __launch_bounds__(kSelThreads) void sel_scatter_kernel(SelLaunch S) {
     keys[i] = -1;
     sums[i] = 0ull;
   }
+  if constexpr (LDS_VIEWS)
+    for (int i = threadIdx.x; i < S.n_views; i += kSelThreads) lviews[i] = S.views[i];
   __syncthreads();
   for (int64_t b0 = (int64_t)blockIdx.x * kChunk; b0 < S.n_contrib; b0 += (int64_t)gridDim.x * kChunk) {
     const int64_t b1 = b0 + kChunk < S.n_contrib ? b0 + kChunk : S.n_contrib;
-    for (int64_t c0 = b0; c0 < b1; c0 += kSelThreads) {
-      const int64_t c = c0 + threadIdx.x;
-      int32_t g = -1;
-      uint64_t q = 0;
+    // software pipeline over the chunk's rounds: while round r's values are
+    // scattered, round r + 1's map value and round r + 2's entries are in
+    // flight (entries past the chunk read as ignored)
+    auto load_entry = [&](int64_t c, int32_t& gi, int32_t& v, int32_t& p, float& w) {
+      gi = -1;
       if (c < b1) {
-        const int32_t gi = S.gauss[c], v = S.view[c], p = S.pixel[c];
-        if (gi >= 0 && gi < N && v >= 0 && v < S.n_views) {             // else outside the live set: ignored
-          const SelView sv = S.views[v];
-          if (p >= 0 && (int64_t)p < sv.pixels) {
-            g = gi;
-            const float e = S.maps[sv.out_offset + p] * S.weight[c];   // one FP32 product
-            if (e > 0.0f) q = (uint64_t)floorf(e * 4294967296.0f);       // exact: a power-of-two scale
-          }
+        gi = S.gauss[c]; v = S.view[c]; p = S.pixel[c]; w = S.weight[c];
+      }
+    };
+    // the contribution's map value (0 for an ignored entry) and its Gaussian (-1)
+    auto map_value = [&](int32_t gi, int32_t v, int32_t p, float w, int32_t& g) -> float {
+      g = -1;
+      if (gi >= 0 && gi < N && v >= 0 && v < S.n_views) {                 // else outside the live set: ignored
+        const SelView sv = LDS_VIEWS ? lviews[v] : S.views[v];
+        if (p >= 0 && (int64_t)p < sv.pixels) {
+          g = gi;
+          return S.maps[sv.out_offset + p] * w;                            // one FP32 product
         }
       }
+      return 0.0f;
+    };
+    int32_t gi1 = -1, v1 = 0, p1 = 0, gi2 = -1, v2 = 0, p2 = 0, g1 = -1;
+    float w1 = 0.0f, w2 = 0.0f;
+    load_entry(b0 + threadIdx.x, gi1, v1, p1, w1);
+    load_entry(b0 + kSelThreads + threadIdx.x, gi2, v2, p2, w2);
+    float e1 = map_value(gi1, v1, p1, w1, g1);
+    for (int64_t c0 = b0; c0 < b1; c0 += kSelThreads) {
+      const int32_t g = g1;
+      const float e = e1;
+      e1 = map_value(gi2, v2, p2, w2, g1);                                 // round r + 1
+      load_entry(c0 + 2 * kSelThreads + threadIdx.x, gi2, v2, p2, w2);    // round r + 2
+      uint64_t q = 0;
+      if (e > 0.0f) q = (uint64_t)floorf(e * 4294967296.0f);               // exact: a power-of-two scale
       const int32_t gp = __shfl_up(g, 1, 64);
       const bool head = lane == 0 || gp != g;
       const uint64_t heads = __ballot(head);
@@ -361,8 +387,11 @@ hipError_t launch_select(const SelLaunch& S, hipStream_t s) {
   hipLaunchKernelGGL(sel_clear_kernel, dim3(grid), dim3(kSelThreads), 0, s, S);
   if (S.n_contrib > 0) {
     const int64_t chunks = (S.n_contrib + kScatterRounds * kSelThreads - 1) / (kScatterRounds * kSelThreads);
-    hipLaunchKernelGGL(sel_scatter_kernel, dim3((unsigned)(chunks < kSelScatterGrid ? chunks : kSelScatterGrid)),
-                       dim3(kSelThreads), 0, s, S);
+    const dim3 g((unsigned)(chunks < kSelScatterGrid ? chunks : kSelScatterGrid));
+    if (S.n_views <= kSelLdsViews)
+      hipLaunchKernelGGL(sel_scatter_kernel<true>, g, dim3(kSelThreads), (size_t)S.n_views * sizeof(SelView), s, S);
+    else
+      hipLaunchKernelGGL(sel_scatter_kernel<false>, g, dim3(kSelThreads), 0, s, S);
   }
   hipLaunchKernelGGL(sel_count_kernel<0>, dim3(grid), dim3(kSelThreads), 0, s, S);
   hipLaunchKernelGGL(sel_scan_kernel<0>, dim3(1), dim3(1024), 0, s, S);
